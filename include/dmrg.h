@@ -1,0 +1,148 @@
+/*
+ * dmrg.h -- C ABI of the MI355X (gfx950) two-site ab initio DMRG sigma library.
+ *
+ * The library computes the hot path of two-site DMRG on the matrix product
+ * state (MPS) of eq. (1) of the paper: the renormalised block operators of
+ * the quantum-chemistry Hamiltonian (Method section; the "DMRG matrix and
+ * tensor algebra" of the Hardware section) and the Davidson sigma step
+ * sigma = H_eff psi on a two-site window.  Quantum numbers are U(1) x U(1):
+ * particle number N and 2*Sz.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Orbitals 0..K-1 are the MPS sites in chain order; spin-orbital
+ *   p = 2*orbital + spin (spin 0 = up, 1 = down).  The local basis of a site
+ *   is |0>, |up>, |dn>, |updn> (indices 0..3) with |updn> = a+_up a+_dn |0>,
+ *   carrying (N, 2Sz) = (0,0), (1,+1), (1,-1), (2,0).
+ * - H = e_core + sum_{pq,s} h_pq a+_{ps} a_{qs}
+ *       + 1/2 sum_{pqrs,st} (pq|rs) a+_{ps} a+_{rt} a_{st} a_{qs}
+ *   with h symmetric (K*K, row-major) and (pq|rs) in chemists' notation
+ *   (K^4, row-major, 8-fold symmetric).
+ * - Bond b (0..K) lies left of site b.  Each bond holds sectors labelled by
+ *   the (N, 2Sz) of the sites left of it, sorted ascending by (N, 2Sz);
+ *   bond 0 is (0,0) with dim 1 and bond K is (N_total, 2Sz_total) with dim 1.
+ * - Site tensor b: blocks (l, n) -> r with Q_l + Q_n = Q_r (l a sector of
+ *   bond b, r of bond b+1), packed by ascending l then n, each block d_l x d_r
+ *   row-major; absent r means absent block.  Sites left of the window are
+ *   left-canonical, sites right of it right-canonical.
+ * - psi of window (i, i+1) ("right-sector-major"): for every sector r of
+ *   bond i+2 in ascending order, the rows (l, n1, n2) with
+ *   Q_l + Q_n1 + Q_n2 = Q_r in ascending (l, n1, n2) order form one dense
+ *   M_r x d_r row-major matrix (the rows of one (l, n1, n2) are d_l
+ *   consecutive rows).  sigma uses the same layout.
+ *
+ * Ownership: the caller owns every buffer it passes; the library copies what
+ * it keeps (integrals, MPS) and never frees caller memory.  The context owns
+ * all derived device state until dmrg_destroy.
+ *
+ * Streams: device work of a context is ordered on the stream given to
+ * dmrg_create (NULL = the null stream).  Device pointers passed to a call must
+ * be valid on that stream.  Calls return after their device work is
+ * enqueued; dmrg_sigma does not synchronise.
+ *
+ * Errors: every call returns a status; < 0 is an error and leaves the
+ * caller's buffers untouched, > 0 a warning.  dmrg_last_error gives the
+ * message.  Arguments are validated on the host before any device work.
+ */
+#ifndef DMRG_H
+#define DMRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dmrg_status;
+#define DMRG_OK 0
+#define DMRG_WARN_NOT_CONVERGED 1
+#define DMRG_ERR_INVALID_ARG (-1)
+#define DMRG_ERR_SHAPE (-2)
+#define DMRG_ERR_HIP (-3)
+#define DMRG_ERR_OOM (-4)
+#define DMRG_ERR_NO_DEVICE (-5)
+#define DMRG_ERR_UNIMPLEMENTED (-6)
+#define DMRG_ERR_STATE (-7)
+
+/* Arithmetic of the sigma contractions. */
+#define DMRG_FP64 0   /* FP64 MFMA, FP64 accumulation */
+#define DMRG_BF16 1   /* BF16 MFMA, FP32 accumulation, FP64 output */
+#define DMRG_BF16X3 2 /* split-BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+
+typedef struct dmrg_ctx_s* dmrg_ctx;
+
+/* Active space and integrals (host pointers, read during the call). */
+typedef struct {
+  int32_t n_orb;   /* K */
+  int32_t n_elec;  /* N, 0 <= N <= 2K */
+  int32_t two_sz;  /* 2*Sz, |2Sz| <= min(N, 2K-N), same parity as N */
+  int32_t pad;
+  double e_core;   /* constant added to every energy */
+  const double* h;   /* K*K */
+  const double* eri; /* K^4, chemists' (pq|rs) */
+} dmrg_problem;
+
+/* U(1) block-sparse MPS (host pointers, copied during the call). */
+typedef struct {
+  int32_t n_sites;              /* K */
+  int32_t window;               /* i: the two-site window is (i, i+1) */
+  const int32_t* bond_offsets;  /* K+2 entries: sectors of bond b are [off[b], off[b+1]) */
+  const int32_t* sector_n;
+  const int32_t* sector_2sz;
+  const int32_t* sector_dim;
+  const double* const* site_data; /* K pointers; entries i and i+1 are ignored */
+} dmrg_mps;
+
+/* Creates a context on HIP device `device`; `stream` is a hipStream_t (may be
+ * NULL).  Fails with DMRG_ERR_NO_DEVICE when no such device exists. */
+dmrg_status dmrg_create(dmrg_ctx* out, int32_t device, void* stream);
+dmrg_status dmrg_destroy(dmrg_ctx ctx);
+/* Message of the last error of ctx (or of the calling thread when ctx is NULL). */
+const char* dmrg_last_error(dmrg_ctx ctx);
+
+/* Builds the renormalised operators for the window (site, site+1)
+ * (Method section; White-Martin / Chan-Head-Gordon normal and complementary
+ * operators): the left block of sites [0, site) and the right block of sites
+ * [site+2, K).  problem / mps may be NULL to keep the ones already loaded
+ * (a new one invalidates every cached block).  direction (+1 / -1 / 0) only
+ * hints which cached blocks to keep.  precision_mask: bit p requests the
+ * operator copies for precision p (bit 0 = FP64 is always built). */
+dmrg_status dmrg_build_ops(dmrg_ctx ctx, const dmrg_problem* problem, const dmrg_mps* mps,
+                           int32_t site, int32_t direction, uint32_t precision_mask);
+
+/* Number of doubles of psi / sigma for the current window. */
+dmrg_status dmrg_psi_size(dmrg_ctx ctx, int64_t* n);
+
+/* sigma = H_eff psi for the current window (device pointers, length
+ * dmrg_psi_size, layout in the header comment).  H_eff is the projection
+ * P^T H P of H onto the window's MPS basis, without e_core. */
+dmrg_status dmrg_sigma(dmrg_ctx ctx, const double* psi, double* sigma, int32_t precision);
+
+typedef struct {
+  double flops;          /* algorithmic FLOPs of one sigma (2*m*n*k over block GEMMs) */
+  double hw_flops;       /* MFMA FLOPs issued (3x flops for DMRG_BF16X3) */
+  int64_t n_pairs;       /* operator pairs (left op, site matrix, right op) */
+  int64_t n_right_ops;   /* distinct right operators contracted first */
+  int64_t n_stage1_tiles, n_stage2_tiles, n_stage2_segments;
+  int64_t workspace_bytes;
+  int64_t operator_bytes; /* device bytes of the left + right block operators */
+  int32_t n_chunks;
+  int32_t pad;
+} dmrg_sigma_info;
+dmrg_status dmrg_sigma_get_info(dmrg_ctx ctx, int32_t precision, dmrg_sigma_info* out);
+
+/* Diagnostic: C = alpha * op(A) op(B) + beta * C with the library's grouped
+ * GEMM kernel of the given precision, for kernel-level numerics tests.
+ * A is m x k (stored k x m when trans_a), B is k x n (stored n x k when
+ * trans_b); row-major device pointers with leading dimensions lda, ldb, ldc.
+ * beta must be 0 or 1.  Stream-ordered, no synchronisation. */
+dmrg_status dmrg_debug_gemm(dmrg_ctx ctx, int32_t m, int32_t n, int32_t k, const double* a,
+                            int32_t lda, int32_t trans_a, const double* b, int32_t ldb,
+                            int32_t trans_b, double* c, int32_t ldc, double alpha, int32_t beta,
+                            int32_t precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMRG_H */

@@ -1,0 +1,188 @@
+"""ctypes binding of the C ABI in include/dmrg.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libdmrg_mi355x.so``; this module
+only converts Python / NumPy / torch arguments to pointers and status codes
+to exceptions.  There is no fallback: if the library is missing or no GPU is
+present, the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmrg_mi355x.so")
+
+DMRG_FP64, DMRG_BF16, DMRG_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": DMRG_FP64, "bf16": DMRG_BF16, "bf16x3": DMRG_BF16X3}
+
+STATUS = {0: "OK", 1: "WARN_NOT_CONVERGED", -1: "INVALID_ARG", -2: "SHAPE", -3: "HIP",
+          -4: "OOM", -5: "NO_DEVICE", -6: "UNIMPLEMENTED", -7: "STATE"}
+
+
+class DMRGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)} ({status}): {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_orb", ctypes.c_int32), ("n_elec", ctypes.c_int32),
+                ("two_sz", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("e_core", ctypes.c_double),
+                ("h", ctypes.POINTER(ctypes.c_double)),
+                ("eri", ctypes.POINTER(ctypes.c_double))]
+
+
+class Mps(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("window", ctypes.c_int32),
+                ("bond_offsets", ctypes.POINTER(ctypes.c_int32)),
+                ("sector_n", ctypes.POINTER(ctypes.c_int32)),
+                ("sector_2sz", ctypes.POINTER(ctypes.c_int32)),
+                ("sector_dim", ctypes.POINTER(ctypes.c_int32)),
+                ("site_data", ctypes.POINTER(ctypes.POINTER(ctypes.c_double)))]
+
+
+class SigmaInfo(ctypes.Structure):
+    _fields_ = [("flops", ctypes.c_double), ("hw_flops", ctypes.c_double),
+                ("n_pairs", ctypes.c_int64), ("n_right_ops", ctypes.c_int64),
+                ("n_stage1_tiles", ctypes.c_int64), ("n_stage2_tiles", ctypes.c_int64),
+                ("n_stage2_segments", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("operator_bytes", ctypes.c_int64), ("n_chunks", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+EXPORTS = {
+    "dmrg_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p]),
+    "dmrg_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
+    "dmrg_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "dmrg_build_ops": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Mps),
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
+    "dmrg_psi_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "dmrg_sigma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "dmrg_sigma_get_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SigmaInfo)]),
+    "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.c_int32]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(
+            f"{path} is missing: build it with `python -m paper_2603_28648_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ctype=ctypes.c_double):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _dev_ptr(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context on one GPU, ordered on torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        self.lib = load_library()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        self._check(self.lib.dmrg_create(ctypes.byref(h), int(device), ctypes.c_void_p(stream)), None)
+        self.h = h
+        self._keep = []
+
+    def _check(self, st, h):
+        if st < 0:
+            raise DMRGError(st, self.lib.dmrg_last_error(h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dmrg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_ops(self, site, direction=0, h=None, eri=None, n_elec=None, two_sz=None,
+                  mps_arrays=None, window=None, e_core=0.0, precision_mask=1):
+        prob = None
+        keep = []
+        if h is not None:
+            h = np.ascontiguousarray(h, dtype=np.float64)
+            eri = np.ascontiguousarray(eri, dtype=np.float64)
+            keep += [h, eri]
+            prob = Problem(h.shape[0], int(n_elec), int(two_sz), 0, float(e_core), _ptr(h), _ptr(eri))
+        mps = None
+        if mps_arrays is not None:
+            a = mps_arrays
+            K = len(a["sites"])
+            arrs = [np.ascontiguousarray(a[k], dtype=np.int32)
+                    for k in ("bond_offsets", "sector_n", "sector_2sz", "sector_dim")]
+            keep += arrs
+            ptrs = (ctypes.POINTER(ctypes.c_double) * K)()
+            for b, s in enumerate(a["sites"]):
+                if s is not None:
+                    s = np.ascontiguousarray(s, dtype=np.float64)
+                    keep.append(s)
+                    ptrs[b] = _ptr(s)
+            keep.append(ptrs)
+            mps = Mps(K, int(site if window is None else window), *[_ptr(x, ctypes.c_int32) for x in arrs],
+                      ctypes.cast(ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))))
+        st = self.lib.dmrg_build_ops(self.h, ctypes.byref(prob) if prob else None,
+                                     ctypes.byref(mps) if mps else None, int(site), int(direction),
+                                     int(precision_mask))
+        self._check(st, self.h)
+        return st
+
+    def psi_size(self):
+        n = ctypes.c_int64()
+        self._check(self.lib.dmrg_psi_size(self.h, ctypes.byref(n)), self.h)
+        return n.value
+
+    def sigma(self, psi, out, precision="fp64"):
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self._check(self.lib.dmrg_sigma(self.h, _dev_ptr(psi), _dev_ptr(out), p), self.h)
+        return out
+
+    def debug_gemm(self, a, b, c, trans_a=False, trans_b=False, alpha=1.0, beta=0,
+                   precision="fp64"):
+        """c = alpha op(a) op(b) + beta c with the library's GEMM kernel (2-D tensors)."""
+        m, n = c.shape
+        k = a.shape[0] if trans_a else a.shape[1]
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        st = self.lib.dmrg_debug_gemm(self.h, m, n, k, _dev_ptr(a), a.stride(0), int(trans_a),
+                                      _dev_ptr(b), b.stride(0), int(trans_b), _dev_ptr(c),
+                                      c.stride(0), float(alpha), int(beta), p)
+        self._check(st, self.h)
+        return c
+
+    def sigma_info(self, precision="fp64"):
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        info = SigmaInfo()
+        self._check(self.lib.dmrg_sigma_get_info(self.h, p, ctypes.byref(info)), self.h)
+        return {k: getattr(info, k) for k, _ in SigmaInfo._fields_ if k != "pad"}

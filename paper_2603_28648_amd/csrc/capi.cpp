@@ -1,0 +1,264 @@
+// C ABI of the library (see include/dmrg.h).  Arguments are validated on the
+// host before any device work; exceptions never cross the ABI.
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+
+#include "../../include/dmrg.h"
+#include "engine.h"
+
+using namespace dmrg;
+
+struct dmrg_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool have_problem = false, have_mps = false;
+  Problem P;
+  Mps m;
+  int window = -1;
+  std::map<int, std::unique_ptr<Env>> left, right;  // by bond
+  std::unique_ptr<SigmaPlan> plan;
+  DevBuf desc;
+  int64_t ws_budget = (int64_t)1 << 30;  // doubles of sigma intermediates (8 GiB)
+};
+
+static thread_local std::string g_err;
+
+static dmrg_status fail(dmrg_ctx c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  g_err = msg;
+  return code;
+}
+
+template <class F>
+static dmrg_status guarded(dmrg_ctx c, F&& f) {
+  try {
+    if (c) DMRG_HIP(hipSetDevice(c->device));
+    return f();
+  } catch (const Error& e) {
+    return fail(c, e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(c, kErrOom, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(c, kErrState, e.what());
+  }
+}
+
+extern "C" {
+
+dmrg_status dmrg_create(dmrg_ctx* out, int32_t device, void* stream) {
+  if (!out) return fail(nullptr, kErrInvalidArg, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+    return fail(nullptr, kErrNoDevice, "no HIP device");
+  if (device < 0 || device >= n) return fail(nullptr, kErrNoDevice, "device index out of range");
+  auto c = new (std::nothrow) dmrg_ctx_s;
+  if (!c) return fail(nullptr, kErrOom, "host allocation failed");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (const char* b = std::getenv("DMRG_WS_BUDGET_MB")) c->ws_budget = std::atoll(b) * (1 << 17);
+  *out = c;
+  return kOk;
+}
+
+dmrg_status dmrg_destroy(dmrg_ctx c) {
+  if (!c) return kOk;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+  return kOk;
+}
+
+const char* dmrg_last_error(dmrg_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+static void load_problem(dmrg_ctx c, const dmrg_problem* p) {
+  DMRG_REQUIRE(p->h && p->eri, kErrInvalidArg, "problem: h and eri must be non-NULL");
+  const int K = p->n_orb, N = p->n_elec, t = p->two_sz;
+  DMRG_REQUIRE(K >= 2 && K <= 127, kErrInvalidArg, "problem: need 2 <= n_orb <= 127");
+  DMRG_REQUIRE(N >= 0 && N <= 2 * K, kErrInvalidArg, "problem: need 0 <= n_elec <= 2*n_orb");
+  DMRG_REQUIRE(((N - t) % 2) == 0, kErrInvalidArg, "problem: n_elec and two_sz must have equal parity");
+  DMRG_REQUIRE(std::abs(t) <= std::min(N, 2 * K - N), kErrInvalidArg, "problem: |two_sz| too large");
+  c->P.K = K;
+  c->P.N = N;
+  c->P.tsz = t;
+  c->P.e_core = p->e_core;
+  c->P.h.assign(p->h, p->h + (size_t)K * K);
+  c->P.eri.assign(p->eri, p->eri + (size_t)K * K * K * K);
+  c->have_problem = true;
+}
+
+static void load_mps(dmrg_ctx c, const dmrg_mps* q) {
+  DMRG_REQUIRE(c->have_problem, kErrState, "mps: load a problem first");
+  const int K = c->P.K;
+  DMRG_REQUIRE(q->n_sites == K, kErrShape, "mps: n_sites differs from n_orb");
+  DMRG_REQUIRE(q->bond_offsets && q->sector_n && q->sector_2sz && q->sector_dim && q->site_data,
+               kErrInvalidArg, "mps: NULL array");
+  DMRG_REQUIRE(q->window >= 0 && q->window <= K - 2, kErrInvalidArg, "mps: window out of range");
+  Mps m;
+  m.K = K;
+  m.N = c->P.N;
+  m.tsz = c->P.tsz;
+  m.bonds.resize(K + 1);
+  for (int b = 0; b <= K; ++b) {
+    const int s0 = q->bond_offsets[b], s1 = q->bond_offsets[b + 1];
+    DMRG_REQUIRE(s0 >= 0 && s1 >= s0, kErrShape, "mps: bond offsets must be non-decreasing");
+    Bond& B = m.bonds[b];
+    for (int s = s0; s < s1; ++s) {
+      QN x{q->sector_n[s], q->sector_2sz[s]};
+      DMRG_REQUIRE(q->sector_dim[s] > 0, kErrShape, "mps: sector dims must be positive");
+      DMRG_REQUIRE(B.q.empty() || B.q.back() < x, kErrShape, "mps: sectors must be sorted and unique");
+      B.q.push_back(x);
+      B.d.push_back(q->sector_dim[s]);
+    }
+    B.finish();
+  }
+  DMRG_REQUIRE(m.bonds[0].size() == 1 && m.bonds[0].q[0] == (QN{0, 0}) && m.bonds[0].d[0] == 1,
+               kErrShape, "mps: bond 0 must be (0,0) of dim 1");
+  DMRG_REQUIRE(m.bonds[K].size() == 1 && m.bonds[K].q[0] == (QN{c->P.N, c->P.tsz}) && m.bonds[K].d[0] == 1,
+               kErrShape, "mps: bond K must be (N, 2Sz) of dim 1");
+  m.site.resize(K);
+  for (int b = 0; b < K; ++b) {
+    if (b == q->window || b == q->window + 1) continue;
+    const double* src = q->site_data[b];
+    DMRG_REQUIRE(src, kErrInvalidArg, "mps: site tensor pointer is NULL");
+    const Bond &L = m.bonds[b], &R = m.bonds[b + 1];
+    SiteTensor& st = m.site[b];
+    st.off.assign(4 * L.size(), -1);
+    int64_t off = 0;
+    for (size_t l = 0; l < L.size(); ++l)
+      for (int n = 0; n < 4; ++n) {
+        int r = R.find(L.q[l] + kSiteQN[n]);
+        if (r < 0) continue;
+        st.off[4 * l + n] = off;
+        off += (int64_t)L.d[l] * R.d[r];
+      }
+    st.data.alloc((size_t)std::max<int64_t>(off, 1) * sizeof(double));
+    DMRG_HIP(hipMemcpy(st.data.p, src, off * sizeof(double), hipMemcpyHostToDevice));
+  }
+  c->m = std::move(m);
+  c->window = q->window;
+  c->have_mps = true;
+  c->left.clear();
+  c->right.clear();
+  c->plan.reset();
+}
+
+dmrg_status dmrg_build_ops(dmrg_ctx c, const dmrg_problem* problem, const dmrg_mps* mps,
+                           int32_t site, int32_t direction, uint32_t precision_mask) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    if (problem) {
+      load_problem(c, problem);
+      c->have_mps = false;
+      c->left.clear();
+      c->right.clear();
+      c->plan.reset();
+    }
+    DMRG_REQUIRE(c->have_problem, kErrState, "build_ops: no problem loaded");
+    DMRG_REQUIRE(mps || c->have_mps, kErrState, "build_ops: no MPS loaded");
+    const int K = c->P.K;
+    DMRG_REQUIRE(site >= 0 && site <= K - 2, kErrInvalidArg, "build_ops: site out of range");
+    DMRG_REQUIRE(direction >= -1 && direction <= 1, kErrInvalidArg, "build_ops: direction must be -1, 0 or +1");
+    DMRG_REQUIRE((precision_mask & ~7u) == 0, kErrInvalidArg, "build_ops: unknown precision bits");
+    if (mps) {
+      DMRG_REQUIRE(mps->window == site, kErrInvalidArg, "build_ops: mps.window must equal site");
+      load_mps(c, mps);
+    }
+    DMRG_REQUIRE(c->window == site, kErrState, "build_ops: the loaded MPS has a different window");
+    hipStream_t s = c->stream;
+    // left block at bond `site`
+    // (older blocks are released as soon as the next one exists)
+    c->plan.reset();
+    if (!c->left.count(site)) {
+      int b = site;
+      while (b > 0 && !c->left.count(b)) --b;
+      std::unique_ptr<Env> cur = c->left.count(b) ? std::move(c->left[b]) : left_start(c->m, s);
+      c->left.erase(b);
+      for (; b < site; ++b) cur = grow_left(c->P, c->m, *cur, c->desc, s);
+      c->left[site] = std::move(cur);
+    }
+    if (!c->right.count(site + 2)) {
+      int b = site + 2;
+      while (b < K && !c->right.count(b)) ++b;
+      std::unique_ptr<Env> cur = c->right.count(b) ? std::move(c->right[b]) : right_start(c->m, s);
+      c->right.erase(b);
+      for (; b > site + 2; --b) cur = grow_right(c->P, c->m, *cur, c->desc, s);
+      c->right[site + 2] = std::move(cur);
+    }
+    // keep only the blocks that bracket this window
+    for (auto it = c->left.begin(); it != c->left.end();)
+      it = (it->first != site) ? c->left.erase(it) : std::next(it);
+    for (auto it = c->right.begin(); it != c->right.end();)
+      it = (it->first != site + 2) ? c->right.erase(it) : std::next(it);
+    c->plan = plan_sigma(c->P, c->m, *c->left[site], *c->right[site + 2], c->ws_budget, s);
+    DMRG_HIP(hipStreamSynchronize(s));
+    (void)precision_mask;
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_psi_size(dmrg_ctx c, int64_t* n) {
+  if (!c || !n) return fail(c, kErrInvalidArg, "NULL argument");
+  if (!c->plan) return fail(c, kErrState, "psi_size: call dmrg_build_ops first");
+  *n = c->plan->psi.size;
+  return kOk;
+}
+
+dmrg_status dmrg_sigma(dmrg_ctx c, const double* psi, double* sigma, int32_t precision) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->plan, kErrState, "sigma: call dmrg_build_ops first");
+    DMRG_REQUIRE(psi && sigma, kErrInvalidArg, "sigma: NULL buffer");
+    DMRG_REQUIRE(precision >= 0 && precision <= 2, kErrInvalidArg, "sigma: unknown precision");
+    if (precision != DMRG_FP64) throw Error(kErrUnimplemented, "sigma: only DMRG_FP64 is available");
+    run_sigma(*c->plan, psi, sigma, c->stream);
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* out) {
+  if (!c || !out) return fail(c, kErrInvalidArg, "NULL argument");
+  if (!c->plan) return fail(c, kErrState, "sigma_get_info: call dmrg_build_ops first");
+  std::memset(out, 0, sizeof(*out));
+  const SigmaPlan& p = *c->plan;
+  out->flops = p.flops;
+  out->hw_flops = precision == DMRG_BF16X3 ? 3 * p.flops : p.flops;
+  out->n_pairs = (int64_t)p.pairs.size();
+  out->n_right_ops = (int64_t)p.zops.size();
+  for (auto& g : p.stage1) out->n_stage1_tiles += (int64_t)g.ntiles;
+  for (auto& g : p.stage2) {
+    out->n_stage2_tiles += (int64_t)g.ntiles;
+    out->n_stage2_segments += (int64_t)g.nsegs;
+  }
+  out->workspace_bytes = p.ws_doubles * 8;
+  out->n_chunks = (int32_t)p.stage1.size();
+  for (auto& kv : c->left) out->operator_bytes += (int64_t)kv.second->bytes();
+  for (auto& kv : c->right) out->operator_bytes += (int64_t)kv.second->bytes();
+  if (p.psums) out->operator_bytes += (int64_t)p.psums->bytes();
+  return kOk;
+}
+
+dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const double* a,
+                            int32_t lda, int32_t trans_a, const double* b, int32_t ldb,
+                            int32_t trans_b, double* cc, int32_t ldc, double alpha, int32_t beta,
+                            int32_t precision) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(a && b && cc, kErrInvalidArg, "debug_gemm: NULL pointer");
+    DMRG_REQUIRE(m > 0 && n > 0 && k > 0, kErrInvalidArg, "debug_gemm: sizes must be positive");
+    DMRG_REQUIRE(beta == 0 || beta == 1, kErrInvalidArg, "debug_gemm: beta must be 0 or 1");
+    DMRG_REQUIRE(lda >= (trans_a ? m : k) && ldb >= (trans_b ? k : n) && ldc >= n, kErrInvalidArg,
+                 "debug_gemm: leading dimension too small");
+    DMRG_REQUIRE(precision == DMRG_FP64, kErrUnimplemented, "debug_gemm: only DMRG_FP64 is available");
+    GemmBatch bt;
+    bt.segs.push_back({a, b, lda, ldb, k, (trans_a ? kTransA : 0) | (trans_b ? kTransB : 0), alpha});
+    bt.add_problem(cc, ldc, m, n, 0, 1, beta);
+    launch_gemm_f64(bt, c->desc, c->stream);
+    return kOk;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,812 @@
+// Construction of renormalised block operators and the two-site sigma plan.
+//
+// Every operator of a block is either a normal-ordered string of at most two
+// creation/annihilation operators, the block Hamiltonian, the identity, or a
+// "complementary" sum of Hamiltonian terms (standard ab initio DMRG: White and
+// Martin 1999; Chan and Head-Gordon 2002).  All of them are derived from one
+// rule: split every term of H by the regions of its spin-orbitals (block,
+// site, rest) with the Jordan-Wigner exchange sign, and route the block part
+// either to a stored operator or to a linear combination of stored operators.
+//
+//   left block  (sites [0, b)): identity, H, strings of length 1 and 2,
+//               T(w) = sum over three-operator block parts x of coef(x w) x,
+//               for every one-operator string w outside the block;
+//   right block (sites [b, K)): identity, H, strings of length 1,
+//               S(w) = sum over one- and three-operator parts (w outside),
+//               Q(w) = sum over two-operator parts (w a two-operator string).
+//
+// A new block operator is sum_c coef_c * Proj(X_c (x) y_c) with X_c an old
+// block operator and y_c a 4x4 site matrix; Proj is the projection with the
+// site tensor (A^T (X (x) y) A on the left, B (y (x) X) B^T on the right).
+// Linear combinations are dense GEMMs over operator classes (operators with
+// the same quantum-number change share one block layout); projections are
+// two-stage grouped GEMMs.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <set>
+#include <tuple>
+
+namespace dmrg {
+
+// ---------------------------------------------------------------------------
+void Env::allocate(hipStream_t s) {
+  for (auto& c : classes) {
+    c->data.alloc((size_t)std::max<int64_t>(1, c->nops * c->L.nnz) * sizeof(double));
+    launch_fill(c->data.as<double>(), 0.0, c->nops * c->L.nnz, s);
+  }
+}
+
+// Writes the exact identity into the registered identity operator.
+static void set_identity(Env& e, hipStream_t s) {
+  const OpRef* r = e.get({kIdent, 0});
+  if (!r) return;
+  OpClass& c = *e.classes[r->cls];
+  std::vector<double> h((size_t)c.L.nnz, 0.0);
+  for (auto& b : c.L.blk)
+    for (int i = 0; i < b.dr; ++i) h[(size_t)b.off + (size_t)i * b.dc + i] = 1.0;
+  DMRG_HIP(hipStreamSynchronize(s));
+  DMRG_HIP(hipMemcpy(c.op(r->idx), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+}
+
+// All canonical strings with n operators over the spin-orbitals `so`.
+static void strings_over(const std::vector<int>& so, int n, std::vector<Str>& out) {
+  const int m = (int)so.size();
+  for (int nc = 0; nc <= n; ++nc) {
+    int na = n - nc;
+    if (nc > m || na > m) continue;
+    std::vector<int> ci(nc), ai(na);
+    // enumerate combinations
+    std::function<void(int, int, std::vector<int>&, std::vector<std::vector<int>>&)> comb;
+    comb = [&](int start, int k, std::vector<int>& cur, std::vector<std::vector<int>>& res) {
+      if ((int)cur.size() == k) { res.push_back(cur); return; }
+      for (int x = start; x < m; ++x) { cur.push_back(x); comb(x + 1, k, cur, res); cur.pop_back(); }
+    };
+    std::vector<std::vector<int>> cs, as;
+    std::vector<int> cur;
+    comb(0, nc, cur, cs);
+    comb(0, na, cur, as);
+    for (auto& c : cs)
+      for (auto& a : as) {
+        Str s;
+        for (int x : c) s.push(so[x], 1);
+        for (int x : a) s.push(so[x], 0);
+        out.push_back(s);
+      }
+  }
+}
+
+static std::unique_ptr<Env> start_env(const Mps& m, int side, hipStream_t s) {
+  auto e = std::make_unique<Env>();
+  e->side = side;
+  e->bond = side > 0 ? 0 : m.K;
+  e->basis = m.bonds[e->bond];
+  e->add({kIdent, 0}, QN{0, 0});
+  e->allocate(s);
+  set_identity(*e, s);
+  return e;
+}
+std::unique_ptr<Env> left_start(const Mps& m, hipStream_t s) { return start_env(m, +1, s); }
+std::unique_ptr<Env> right_start(const Mps& m, hipStream_t s) { return start_env(m, -1, s); }
+
+// ---------------------------------------------------------------------------
+// Components and their execution.
+namespace {
+
+struct Target {
+  OpRef ref;
+};
+
+using CompMap = std::map<std::tuple<int, int, int, int, uint64_t>, double>;
+// key: (target cls, target idx, source cls, source idx, site-string key)
+
+void add_comp(CompMap& cm, const OpRef& t, const OpRef* src, const Str& y, double c) {
+  if (!src || c == 0.0) return;
+  cm[std::make_tuple(t.cls, t.idx, src->cls, src->idx, y.key())] += c;
+}
+
+struct Projection {
+  const double* src;
+  const Layout* sl;
+  Mat4 y;
+  int ypar;
+  double* dst;
+  const Layout* dl;
+  double alpha;
+};
+
+// Emits the two-stage GEMMs of a list of projections, in chunks bounded by the
+// intermediate workspace, and runs them.
+void run_projections(int side, const Mps& m, int site, const std::vector<Projection>& projs,
+                     DevBuf& desc, DevBuf& uws, int64_t budget, hipStream_t s) {
+  const SiteTensor& st = m.site[site];
+  const double* S = st.data.as<double>();
+  const Bond& oldb = side > 0 ? m.bonds[site] : m.bonds[site + 1];
+  const Bond& newb = side > 0 ? m.bonds[site + 1] : m.bonds[site];
+  size_t p = 0;
+  while (p < projs.size()) {
+    // size the chunk
+    int64_t need = 0;
+    size_t q = p;
+    for (; q < projs.size(); ++q) {
+      int64_t u = 0;
+      const Projection& pr = projs[q];
+      for (auto& tb : pr.dl->blk)
+        for (int n = 0; n < 4; ++n)
+          for (int np = 0; np < 4; ++np) {
+            if (pr.y.m[np][n] == 0) continue;
+            if (side > 0) {
+              int lp = oldb.find(newb.q[tb.r] - kSiteQN[np]);
+              if (lp >= 0) u += (int64_t)oldb.d[lp] * newb.d[tb.c];
+            } else {
+              int rp = oldb.find(newb.q[tb.r] + kSiteQN[np]);
+              if (rp >= 0) u += (int64_t)oldb.d[rp] * newb.d[tb.c];
+            }
+          }
+      if (q > p && need + u > budget) break;
+      need += u;
+    }
+    if ((int64_t)(uws.bytes / sizeof(double)) < need) {
+      DMRG_HIP(hipStreamSynchronize(s));
+      uws.alloc((size_t)std::max<int64_t>(need, 1) * sizeof(double));
+    }
+    double* U = uws.as<double>();
+    int64_t uoff = 0;
+    GemmBatch b1, b2;
+    for (size_t k = p; k < q; ++k) {
+      const Projection& pr = projs[k];
+      const int xpar = pr.sl->dq.n & 1;
+      for (auto& tb : pr.dl->blk) {
+        const size_t s0 = b2.segs.size();
+        for (int n = 0; n < 4; ++n)
+          for (int np = 0; np < 4; ++np) {
+            const double yv = pr.y.m[np][n];
+            if (yv == 0) continue;
+            if (side > 0) {
+              // target (r', r) = (tb.r, tb.c) on the new bond
+              const int r = tb.c, rp = tb.r;
+              const int l = oldb.find(newb.q[r] - kSiteQN[n]);
+              const int lp = oldb.find(newb.q[rp] - kSiteQN[np]);
+              if (l < 0 || lp < 0) continue;
+              const Layout::Blk* xb = pr.sl->col(l);
+              if (!xb || xb->r != lp) continue;
+              const int64_t oa = st.off[4 * l + n], oap = st.off[4 * lp + np];
+              if (oa < 0 || oap < 0) continue;
+              const int dl = oldb.d[l], dlp = oldb.d[lp], dr = newb.d[r], drp = newb.d[rp];
+              double* u = U + uoff;
+              uoff += (int64_t)dlp * dr;
+              const size_t t0 = b1.segs.size();
+              b1.segs.push_back({pr.src + xb->off, S + oa, dl, dr, dl, 0, 1.0});
+              b1.add_problem(u, dr, dlp, dr, t0, t0 + 1, 0);
+              double sg = ((pr.ypar & 1) && (oldb.q[l].n & 1)) ? -1.0 : 1.0;
+              b2.segs.push_back({S + oap, u, drp, dr, dlp, kTransA, pr.alpha * yv * sg});
+            } else {
+              // target (l', l) = (tb.r, tb.c) on the new bond
+              const int l = tb.c, lp = tb.r;
+              const int r = oldb.find(newb.q[l] + kSiteQN[n]);
+              const int rp = oldb.find(newb.q[lp] + kSiteQN[np]);
+              if (r < 0 || rp < 0) continue;
+              const Layout::Blk* xb = pr.sl->col(r);
+              if (!xb || xb->r != rp) continue;
+              const int64_t ob = st.off[4 * l + n], obp = st.off[4 * lp + np];
+              if (ob < 0 || obp < 0) continue;
+              const int dr = oldb.d[r], drp = oldb.d[rp], dl = newb.d[l], dlp = newb.d[lp];
+              double* u = U + uoff;
+              uoff += (int64_t)drp * dl;
+              const size_t t0 = b1.segs.size();
+              b1.segs.push_back({pr.src + xb->off, S + ob, dr, dr, dr, kTransB, 1.0});
+              b1.add_problem(u, dl, drp, dl, t0, t0 + 1, 0);
+              double sg = (xpar && (kSiteN[n] & 1)) ? -1.0 : 1.0;
+              b2.segs.push_back({S + obp, u, drp, dl, drp, 0, pr.alpha * yv * sg});
+            }
+          }
+        const size_t s1 = b2.segs.size();
+        b2.add_problem(pr.dst + tb.off, tb.dc, tb.dr, tb.dc, s0, s1, 1);
+      }
+    }
+    launch_gemm_f64(b1, desc, s);
+    launch_gemm_f64(b2, desc, s);
+    p = q;
+  }
+}
+
+// Executes all components: new = sum coef * Proj(old (x) y).
+void execute(const Env& old, Env& neu, const CompMap& cm, const Mps& m, int site,
+             DevBuf& desc, hipStream_t s) {
+  const int64_t kBudget = (int64_t)1 << 28;  // doubles of intermediates per chunk (2 GiB)
+  // group by (target class, site string, source class)
+  struct Group {
+    std::map<int, std::vector<std::pair<int, double>>> by_t;  // target idx -> (src idx, c)
+    std::set<int> srcs;
+  };
+  std::map<std::tuple<int, uint64_t, int>, Group> groups;
+  for (auto& kv : cm) {
+    int tc, ti, sc, si;
+    uint64_t yk;
+    std::tie(tc, ti, sc, si, yk) = kv.first;
+    if (kv.second == 0.0) continue;
+    Group& g = groups[std::make_tuple(tc, yk, sc)];
+    g.by_t[ti].push_back({si, kv.second});
+    g.srcs.insert(si);
+  }
+  DevBuf uws, tmp, coef;
+  std::vector<Projection> direct;
+  for (auto& gk : groups) {
+    const int tc = std::get<0>(gk.first), sc = std::get<2>(gk.first);
+    const Str ys = Str::from_key(std::get<1>(gk.first));
+    const Mat4 y = site_matrix(ys);
+    const int ypar = ys.parity();
+    Group& g = gk.second;
+    OpClass& T = *neu.classes[tc];
+    const OpClass& S = *old.classes[sc];
+    bool single = true;
+    for (auto& t : g.by_t) single = single && t.second.size() == 1;
+    const int nt = (int)g.by_t.size(), ns = (int)g.srcs.size();
+    if (single) {
+      for (auto& t : g.by_t)
+        direct.push_back({S.op(t.second[0].first), &S.L, y, ypar, T.op(t.first), &T.L,
+                          t.second[0].second});
+      continue;
+    }
+    if (nt <= ns) {
+      // sum first: X (nt x nnz_src) = Coef (nt x nops_src) * S, then project
+      std::vector<double> C((size_t)nt * S.nops, 0.0);
+      int row = 0;
+      std::vector<int> tids;
+      for (auto& t : g.by_t) {
+        for (auto& sc2 : t.second) C[(size_t)row * S.nops + sc2.first] += sc2.second;
+        tids.push_back(t.first);
+        ++row;
+      }
+      DMRG_HIP(hipStreamSynchronize(s));
+      coef.alloc(C.size() * sizeof(double));
+      DMRG_HIP(hipMemcpy(coef.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
+      tmp.alloc((size_t)std::max<int64_t>(1, (int64_t)nt * S.L.nnz) * sizeof(double));
+      GemmBatch b;
+      b.segs.push_back({coef.p, S.data.p, S.nops, (int)S.L.nnz, S.nops, 0, 1.0});
+      b.add_problem(tmp.p, (int)S.L.nnz, nt, (int)S.L.nnz, 0, 1, 0);
+      launch_gemm_f64(b, desc, s);
+      std::vector<Projection> pj;
+      for (int k = 0; k < nt; ++k)
+        pj.push_back({tmp.as<double>() + (int64_t)k * S.L.nnz, &S.L, y, ypar, T.op(tids[k]), &T.L, 1.0});
+      run_projections(neu.side, m, site, pj, desc, uws, kBudget, s);
+      DMRG_HIP(hipStreamSynchronize(s));
+    } else {
+      // project first: P (ns x nnz_tgt) = Proj(S_j (x) y), then T += Coef * P
+      std::vector<int> sids(g.srcs.begin(), g.srcs.end());
+      std::map<int, int> spos;
+      for (int k = 0; k < ns; ++k) spos[sids[k]] = k;
+      int t0 = g.by_t.begin()->first, t1 = g.by_t.rbegin()->first + 1;
+      std::vector<double> C((size_t)(t1 - t0) * ns, 0.0);
+      for (auto& t : g.by_t)
+        for (auto& sc2 : t.second) C[(size_t)(t.first - t0) * ns + spos[sc2.first]] += sc2.second;
+      DMRG_HIP(hipStreamSynchronize(s));
+      tmp.alloc((size_t)std::max<int64_t>(1, (int64_t)ns * T.L.nnz) * sizeof(double));
+      launch_fill(tmp.as<double>(), 0.0, (int64_t)ns * T.L.nnz, s);
+      std::vector<Projection> pj;
+      for (int k = 0; k < ns; ++k)
+        pj.push_back({S.op(sids[k]), &S.L, y, ypar, tmp.as<double>() + (int64_t)k * T.L.nnz, &T.L, 1.0});
+      run_projections(neu.side, m, site, pj, desc, uws, kBudget, s);
+      coef.alloc(C.size() * sizeof(double));
+      DMRG_HIP(hipMemcpy(coef.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
+      GemmBatch b;
+      b.segs.push_back({coef.p, tmp.p, ns, (int)T.L.nnz, ns, 0, 1.0});
+      b.add_problem(T.op(t0), (int)T.L.nnz, t1 - t0, (int)T.L.nnz, 0, 1, 1);
+      launch_gemm_f64(b, desc, s);
+      DMRG_HIP(hipStreamSynchronize(s));
+    }
+  }
+  // direct projections: group so that a target appears once per launch
+  std::sort(direct.begin(), direct.end(),
+            [](const Projection& a, const Projection& b) { return a.dst < b.dst; });
+  std::vector<Projection> batch;
+  std::set<double*> seen;
+  for (auto& pr : direct) {
+    if (seen.count(pr.dst)) {
+      run_projections(neu.side, m, site, batch, desc, uws, kBudget, s);
+      batch.clear();
+      seen.clear();
+    }
+    batch.push_back(pr);
+    seen.insert(pr.dst);
+  }
+  run_projections(neu.side, m, site, batch, desc, uws, kBudget, s);
+  DMRG_HIP(hipStreamSynchronize(s));
+}
+
+std::vector<int> site_so(int b) { return {2 * b, 2 * b + 1}; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+std::unique_ptr<Env> grow_left(const Problem& P, const Mps& m, const Env& old, DevBuf& desc,
+                               hipStream_t s) {
+  const int b = old.bond;
+  DMRG_REQUIRE(old.side > 0 && b < m.K, kErrState, "grow_left: bad block");
+  DMRG_REQUIRE(!m.site[b].off.empty(), kErrState, "grow_left: site tensor missing");
+  auto e = std::make_unique<Env>();
+  e->side = +1;
+  e->bond = b + 1;
+  e->basis = m.bonds[b + 1];
+  const int M = 2 * (b + 1), Mall = 2 * P.K;
+  auto region = [&](int p) { return p < 2 * b ? 0 : (p < M ? 1 : 2); };
+  CompMap cm;
+  const OpRef* oldI = old.get({kIdent, 0});
+  // identity
+  OpRef tI = e->add({kIdent, 0}, QN{0, 0});
+  // normal strings of length 1 and 2
+  std::vector<int> inner(M);
+  for (int p = 0; p < M; ++p) inner[p] = p;
+  std::vector<Str> normals;
+  strings_over(inner, 1, normals);
+  strings_over(inner, 2, normals);
+  for (const Str& x : normals) {
+    OpRef t = e->add({kNormal, x.key()}, x.qn());
+    Str parts[3];
+    int sg = split_regions(x, region, 3, parts);
+    if (sg == 0) continue;
+    const OpRef* src = parts[0].n ? old.get({kNormal, parts[0].key()}) : oldI;
+    add_comp(cm, t, src, parts[1], (double)sg);
+  }
+  // complementary T(w) for one-operator strings w outside
+  for (int p = M; p < Mall; ++p)
+    for (int dag = 0; dag < 2; ++dag) {
+      Str w;
+      w.push(p, dag);
+      e->add({kComp, w.key()}, -w.qn());
+    }
+  OpRef tH = e->add({kHam, 0}, QN{0, 0});
+  // Hamiltonian terms with at most one spatial index outside [0, b]
+  for_each_term(
+      P, [&](const int* ix, int n) {
+        int out = 0;
+        for (int k = 0; k < n; ++k) out += ix[k] > b;
+        return out <= 1;
+      },
+      [&](double c, const Str& term) {
+        Str parts[3];
+        int sg = split_regions(term, region, 3, parts);
+        if (sg == 0) return;
+        const Str &x = parts[0], &y = parts[1], &z = parts[2];
+        OpRef t;
+        if (z.n == 0) t = tH;
+        else if (z.n == 1 && x.n + y.n == 3) t = *e->get({kComp, z.key()});
+        else return;
+        if (x.n == 0) add_comp(cm, t, oldI, y, c * sg);
+        else if (x.n == 3) return;                       // inside T of the old block
+        else if (y.n == 0 && z.n == 0) return;           // inside H of the old block
+        else add_comp(cm, t, old.get({kNormal, x.key()}), y, c * sg);
+      });
+  // pass-through of the old complementary operators and H
+  Str none;
+  add_comp(cm, tH, old.get({kHam, 0}), none, 1.0);
+  std::vector<Str> y1;
+  strings_over(site_so(b), 1, y1);
+  for (const Str& y : y1) add_comp(cm, tH, old.get({kComp, y.key()}), y, 1.0);
+  for (int p = M; p < Mall; ++p)
+    for (int dag = 0; dag < 2; ++dag) {
+      Str w;
+      w.push(p, dag);
+      add_comp(cm, *e->get({kComp, w.key()}), old.get({kComp, w.key()}), none, 1.0);
+    }
+  e->allocate(s);
+  (void)tI;
+  // the identity is exact by construction, not projected
+  CompMap cm2;
+  for (auto& kv : cm)
+    if (!(std::get<0>(kv.first) == tI.cls && std::get<1>(kv.first) == tI.idx)) cm2.insert(kv);
+  execute(old, *e, cm2, m, b, desc, s);
+  set_identity(*e, s);
+  return e;
+}
+
+std::unique_ptr<Env> grow_right(const Problem& P, const Mps& m, const Env& old, DevBuf& desc,
+                                hipStream_t s) {
+  const int b = old.bond - 1;  // the new site
+  DMRG_REQUIRE(old.side < 0 && b >= 0, kErrState, "grow_right: bad block");
+  DMRG_REQUIRE(!m.site[b].off.empty(), kErrState, "grow_right: site tensor missing");
+  auto e = std::make_unique<Env>();
+  e->side = -1;
+  e->bond = b;
+  e->basis = m.bonds[b];
+  const int M0 = 2 * b, Mall = 2 * P.K;
+  auto region = [&](int p) { return p < M0 ? 0 : (p < M0 + 2 ? 1 : 2); };
+  CompMap cm;
+  const OpRef* oldI = old.get({kIdent, 0});
+  OpRef tI = e->add({kIdent, 0}, QN{0, 0});
+  // normal strings of length 1 on [2b, 2K)
+  for (int p = M0; p < Mall; ++p)
+    for (int dag = 0; dag < 2; ++dag) {
+      Str x;
+      x.push(p, dag);
+      OpRef t = e->add({kNormal, x.key()}, x.qn());
+      if (p < M0 + 2) add_comp(cm, t, oldI, x, 1.0);
+      else add_comp(cm, t, old.get({kNormal, x.key()}), Str(), 1.0);
+    }
+  std::vector<int> outer(M0);
+  for (int p = 0; p < M0; ++p) outer[p] = p;
+  std::vector<Str> w1, w2;
+  strings_over(outer, 1, w1);
+  strings_over(outer, 2, w2);
+  for (const Str& w : w1) e->add({kComp, w.key()}, -w.qn());
+  for (const Str& w : w2) e->add({kComp, w.key()}, -w.qn());
+  OpRef tH = e->add({kHam, 0}, QN{0, 0});
+  for_each_term(
+      P, [&](const int* ix, int n) {
+        int out = 0;
+        for (int k = 0; k < n; ++k) out += ix[k] < b;
+        return out <= 2;
+      },
+      [&](double c, const Str& term) {
+        Str parts[3];
+        int sg = split_regions(term, region, 3, parts);
+        if (sg == 0) return;
+        const Str &z = parts[0], &y = parts[1], &x = parts[2];
+        OpRef t;
+        const int inside = y.n + x.n;
+        if (z.n == 0) t = tH;
+        else if (z.n == 1 && (inside == 1 || inside == 3)) t = *e->get({kComp, z.key()});
+        else if (z.n == 2 && inside == 2) t = *e->get({kComp, z.key()});
+        else return;
+        if (x.n == 0) add_comp(cm, t, oldI, y, c * sg);
+        else if (z.n + y.n <= 2) return;                 // inside H, S or Q of the old block
+        else add_comp(cm, t, old.get({kNormal, x.key()}), y, c * sg);
+      });
+  Str none;
+  add_comp(cm, tH, old.get({kHam, 0}), none, 1.0);
+  std::vector<Str> y1, y2;
+  strings_over(site_so(b), 1, y1);
+  strings_over(site_so(b), 2, y2);
+  for (const Str& y : y1) add_comp(cm, tH, old.get({kComp, y.key()}), y, 1.0);
+  for (const Str& y : y2) add_comp(cm, tH, old.get({kComp, y.key()}), y, 1.0);
+  for (const Str& z : w1) {
+    OpRef t = *e->get({kComp, z.key()});
+    add_comp(cm, t, old.get({kComp, z.key()}), none, 1.0);
+    for (const Str& y : y1) {
+      Str w;
+      int eps = concat_canonical(z, y, w);
+      if (eps == 0) continue;
+      add_comp(cm, t, old.get({kComp, w.key()}), y, (double)eps);
+    }
+  }
+  for (const Str& z : w2) add_comp(cm, *e->get({kComp, z.key()}), old.get({kComp, z.key()}), none, 1.0);
+  e->allocate(s);
+  CompMap cm2;
+  for (auto& kv : cm)
+    if (!(std::get<0>(kv.first) == tI.cls && std::get<1>(kv.first) == tI.idx)) cm2.insert(kv);
+  execute(old, *e, cm2, m, b, desc, s);
+  set_identity(*e, s);
+  return e;
+}
+
+// ---------------------------------------------------------------------------
+void PsiLayout::build(const Bond& bl, const Bond& br) {
+  rows_of.assign(br.size(), 0);
+  off.assign(br.size(), 0);
+  row_of.assign(br.size(), {});
+  size = 0;
+  for (size_t r = 0; r < br.size(); ++r) {
+    for (size_t l = 0; l < bl.size(); ++l)
+      for (int n1 = 0; n1 < 4; ++n1)
+        for (int n2 = 0; n2 < 4; ++n2)
+          if (bl.q[l] + kSiteQN[n1] + kSiteQN[n2] == br.q[r]) {
+            row_of[r][{(int)l, 4 * n1 + n2}] = rows_of[r];
+            rows_of[r] += bl.d[l];
+          }
+    off[r] = size;
+    size += rows_of[r] * br.d[r];
+  }
+}
+
+std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env& L, const Env& R,
+                                      int64_t ws_budget, hipStream_t s) {
+  const int i = L.bond;
+  DMRG_REQUIRE(L.side > 0 && R.side < 0 && R.bond == i + 2, kErrState, "plan_sigma: blocks do not bracket a window");
+  auto plan = std::make_unique<SigmaPlan>();
+  plan->window = i;
+  const Bond& bl = m.bonds[i];
+  const Bond& br = m.bonds[i + 2];
+  plan->psi.build(bl, br);
+  const int ML = 2 * i, MS = 2 * i + 4;
+  auto region = [&](int p) { return p < ML ? 0 : (p < MS ? 1 : 2); };
+  const OpRef* LI = L.get({kIdent, 0});
+
+  // ---- pairs -------------------------------------------------------------
+  struct PKey {
+    int lsrc;      // 0 stored L op, 1 partial sum
+    int lcls, lidx;
+    int z;         // R op index or -1
+    bool operator<(const PKey& o) const {
+      return std::tie(lsrc, lcls, lidx, z) < std::tie(o.lsrc, o.lcls, o.lidx, o.z);
+    }
+  };
+  std::map<OpKey, int, bool (*)(const OpKey&, const OpKey&)> zindex(
+      [](const OpKey& a, const OpKey& b) { return std::tie(a.kind, a.s) < std::tie(b.kind, b.s); });
+  std::vector<OpRef> zrefs;
+  auto zid = [&](OpKey k) -> int {
+    const OpRef* r = R.get(k);
+    if (!r) return -2;
+    auto it = zindex.find(k);
+    if (it != zindex.end()) return it->second;
+    int id = (int)zrefs.size();
+    zrefs.push_back(*r);
+    zindex[k] = id;
+    return id;
+  };
+  struct PVal {
+    Mat16 y;
+    int ypar;
+    bool any;
+  };
+  std::map<PKey, PVal> pmap;
+  auto add_pair = [&](int lsrc, OpRef lref, int z, const Str& y, double c) {
+    if (z == -2 || c == 0.0) return;
+    Mat16 Y = two_site_matrix(y, i);
+    PKey k{lsrc, lref.cls, lref.idx, z};
+    auto it = pmap.find(k);
+    if (it == pmap.end()) {
+      PVal v;
+      v.y = Mat16::zero();
+      v.ypar = y.parity();
+      v.any = true;
+      it = pmap.emplace(k, v).first;
+    }
+    DMRG_REQUIRE(it->second.ypar == y.parity(), kErrState, "plan_sigma: parity mix");
+    for (int a = 0; a < 16; ++a)
+      for (int b = 0; b < 16; ++b) it->second.y.m[a][b] += c * Y.m[a][b];
+  };
+  // partial sums W(y, xR) = sum_xL c xL
+  std::map<std::pair<uint64_t, uint64_t>, std::map<std::pair<int, int>, double>> psum;
+  std::map<std::pair<uint64_t, uint64_t>, QN> psum_dq;
+  for_each_term(
+      P, [](const int*, int) { return true; },
+      [&](double c, const Str& term) {
+        Str parts[3];
+        int sg = split_regions(term, region, 3, parts);
+        if (sg == 0) return;
+        const Str &xl = parts[0], &y = parts[1], &xr = parts[2];
+        if (xr.n > 0 && xl.n + y.n <= 2) return;       // right complementary pass-through
+        if (xl.n == 3) return;                          // left T pass-through
+        if (xl.n > 0 && y.n == 0 && xr.n == 0) return;  // left H
+        const OpRef* src = xl.n ? L.get({kNormal, xl.key()}) : LI;
+        DMRG_REQUIRE(src, kErrState, "plan_sigma: missing left operator");
+        auto key = std::make_pair(y.key(), xr.key());
+        psum[key][{src->cls, src->idx}] += c * sg;
+        psum_dq[key] = -(y.qn() + xr.qn());
+      });
+  Str none;
+  // stored pass-through pairs
+  if (const OpRef* h = L.get({kHam, 0})) add_pair(0, *h, -1, none, 1.0);
+  if (LI) add_pair(0, *LI, zid({kHam, 0}), none, 1.0);
+  std::vector<int> sso = {2 * i, 2 * i + 1, 2 * i + 2, 2 * i + 3};
+  std::vector<Str> ys1, ys2, lstr1, lstr2;
+  strings_over(sso, 1, ys1);
+  strings_over(sso, 2, ys2);
+  for (const Str& y : ys1)
+    if (const OpRef* t = L.get({kComp, y.key()})) add_pair(0, *t, -1, y, 1.0);
+  for (int p = MS; p < 2 * P.K; ++p)
+    for (int dag = 0; dag < 2; ++dag) {
+      Str xr;
+      xr.push(p, dag);
+      if (const OpRef* t = L.get({kComp, xr.key()})) add_pair(0, *t, zid({kNormal, xr.key()}), none, 1.0);
+    }
+  std::vector<int> lso(ML);
+  for (int p = 0; p < ML; ++p) lso[p] = p;
+  strings_over(lso, 1, lstr1);
+  strings_over(lso, 2, lstr2);
+  auto rpass = [&](const Str& xl, const Str& y) {
+    Str w;
+    int eps = concat_canonical(xl, y, w);
+    if (eps == 0 || w.n == 0) return;
+    const OpRef* lr = xl.n ? L.get({kNormal, xl.key()}) : LI;
+    if (!lr) return;
+    add_pair(0, *lr, zid({kComp, w.key()}), y, (double)eps);
+  };
+  for (const Str& xl : lstr2) rpass(xl, none);
+  for (const Str& xl : lstr1) {
+    rpass(xl, none);
+    for (const Str& y : ys1) rpass(xl, y);
+  }
+  for (const Str& y : ys1) rpass(none, y);
+  for (const Str& y : ys2) rpass(none, y);
+  // partial sums
+  plan->psums = std::make_unique<Env>();
+  Env& W = *plan->psums;
+  W.side = +1;
+  W.bond = i;
+  W.basis = bl;
+  std::vector<std::pair<std::pair<uint64_t, uint64_t>, OpRef>> wlist;
+  uint64_t wid = 0;
+  for (auto& kv : psum) {
+    OpRef r = W.add({kPsum, wid++}, psum_dq[kv.first]);
+    wlist.push_back({kv.first, r});
+  }
+  W.allocate(s);
+  {
+    // per W class: Coef (nW x nops of the source class) * source class
+    std::map<int, std::vector<std::pair<const std::map<std::pair<int, int>, double>*, int>>> by_cls;
+    for (size_t k = 0; k < wlist.size(); ++k) by_cls[wlist[k].second.cls].push_back({&psum[wlist[k].first], wlist[k].second.idx});
+    DevBuf desc, coef;
+    for (auto& kv : by_cls) {
+      OpClass& Wc = *W.classes[kv.first];
+      // all sources of a W class share one L class (same dq)
+      int scls = -1;
+      for (auto& e : kv.second)
+        for (auto& t : *e.first) {
+          DMRG_REQUIRE(scls < 0 || scls == t.first.first, kErrState, "plan_sigma: mixed source classes");
+          scls = t.first.first;
+        }
+      if (scls < 0) continue;
+      const OpClass& Sc = *L.classes[scls];
+      DMRG_REQUIRE(Sc.L.nnz == Wc.L.nnz, kErrState, "plan_sigma: layout mismatch");
+      std::vector<double> C((size_t)Wc.nops * Sc.nops, 0.0);
+      for (auto& e : kv.second)
+        for (auto& t : *e.first) C[(size_t)e.second * Sc.nops + t.first.second] += t.second;
+      coef.alloc(C.size() * sizeof(double));
+      DMRG_HIP(hipStreamSynchronize(s));
+      DMRG_HIP(hipMemcpy(coef.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
+      GemmBatch b;
+      b.segs.push_back({coef.p, Sc.data.p, Sc.nops, (int)Sc.L.nnz, Sc.nops, 0, 1.0});
+      b.add_problem(Wc.data.p, (int)Wc.L.nnz, Wc.nops, (int)Wc.L.nnz, 0, 1, 0);
+      launch_gemm_f64(b, desc, s);
+    }
+    DMRG_HIP(hipStreamSynchronize(s));
+  }
+  for (auto& w : wlist) {
+    const Str y = Str::from_key(w.first.first), xr = Str::from_key(w.first.second);
+    int z = xr.n ? zid({kNormal, xr.key()}) : -1;
+    add_pair(1, w.second, z, y, 1.0);
+  }
+  // ---- finalise pairs ------------------------------------------------------
+  for (auto& r : zrefs) {
+    const OpClass& c = *R.classes[r.cls];
+    plan->zops.push_back({c.op(r.idx), &c.L});
+    plan->zpar.push_back(c.L.dq.n & 1);
+  }
+  for (auto& kv : pmap) {
+    const PKey& k = kv.first;
+    const Env& src = k.lsrc ? W : L;
+    const OpClass& c = *src.classes[k.lcls];
+    bool nz = false;
+    for (int a = 0; a < 16 && !nz; ++a)
+      for (int b = 0; b < 16; ++b)
+        if (kv.second.y.m[a][b] != 0) { nz = true; break; }
+    if (!nz) continue;
+    plan->pairs.push_back({{c.op(k.lidx), &c.L}, k.z, kv.second.y, kv.second.ypar});
+  }
+
+  // ---- execution schedule ----------------------------------------------------
+  const PsiLayout& ps = plan->psi;
+  plan->psi_in.alloc((size_t)std::max<int64_t>(1, ps.size) * sizeof(double));
+  plan->sigma_out.alloc((size_t)std::max<int64_t>(1, ps.size) * sizeof(double));
+  const double* PSI = plan->psi_in.as<double>();
+  double* SIG = plan->sigma_out.as<double>();
+  // stage-1 sizes per z
+  const int nz = (int)plan->zops.size();
+  std::vector<int64_t> zsize(nz, 0);
+  for (int z = 0; z < nz; ++z)
+    for (auto& blk : plan->zops[z].lay->blk)
+      if (ps.rows_of[blk.c] > 0 && ps.rows_of[blk.r] > 0) zsize[z] += ps.rows_of[blk.c] * br.d[blk.r];
+  // chunks of z
+  std::vector<std::pair<int, int>> chunks;
+  {
+    int z0 = 0;
+    int64_t acc = 0;
+    for (int z = 0; z < nz; ++z) {
+      if (z > z0 && acc + zsize[z] > ws_budget) {
+        chunks.push_back({z0, z});
+        z0 = z;
+        acc = 0;
+      }
+      acc += zsize[z];
+      plan->ws_doubles = std::max(plan->ws_doubles, acc);
+    }
+    chunks.push_back({z0, nz});
+  }
+  plan->ws.alloc((size_t)std::max<int64_t>(1, plan->ws_doubles) * sizeof(double));
+  double* WS = plan->ws.as<double>();
+  // pairs by z
+  std::map<int, std::vector<int>> pairs_of_z;
+  for (size_t k = 0; k < plan->pairs.size(); ++k) pairs_of_z[plan->pairs[k].z].push_back((int)k);
+  for (size_t ci = 0; ci < chunks.size(); ++ci) {
+    const int z0 = chunks[ci].first, z1 = chunks[ci].second;
+    GemmBatch b1;
+    // T_z(r) location: (z, r) -> pointer, width d_r'
+    std::map<std::pair<int, int>, std::pair<double*, int>> tloc;
+    int64_t off = 0;
+    for (int z = z0; z < z1; ++z) {
+      const OpView& Z = plan->zops[z];
+      const double sgn_par = plan->zpar[z];
+      for (auto& blk : Z.lay->blk) {
+        const int r = blk.c, rp = blk.r;
+        if (ps.rows_of[r] == 0 || ps.rows_of[rp] == 0) continue;
+        double* T = WS + off;
+        off += ps.rows_of[r] * br.d[rp];
+        tloc[{z, r}] = {T, br.d[rp]};
+        const double alpha = (sgn_par && (br.q[r].n & 1)) ? -1.0 : 1.0;
+        const size_t s0 = b1.segs.size();
+        b1.segs.push_back({PSI + ps.off[r], Z.data + blk.off, br.d[r], br.d[r], br.d[r], kTransB, alpha});
+        b1.add_problem(T, br.d[rp], (int)ps.rows_of[r], br.d[rp], s0, s0 + 1, 0);
+      }
+    }
+    // stage 2: output rows (r', l', n') collect segments
+    std::map<std::tuple<int, int64_t>, std::vector<GemmSeg>> outs;
+    std::map<std::tuple<int, int64_t>, int> out_m;
+    auto zin = [&](int z) { return z == -1 ? ci == 0 : (z >= z0 && z < z1); };
+    for (auto& pz : pairs_of_z) {
+      if (!zin(pz.first)) continue;
+      for (int k : pz.second) {
+        const SigmaPair& pr = plan->pairs[k];
+        const Layout& Ll = *pr.L.lay;
+        for (int np = 0; np < 16; ++np)
+          for (int n = 0; n < 16; ++n) {
+            const double yv = pr.y.m[np][n];
+            if (yv == 0) continue;
+            const QN qn = kSiteQN[n >> 2] + kSiteQN[n & 3];
+            const QN qnp = kSiteQN[np >> 2] + kSiteQN[np & 3];
+            for (auto& lb : Ll.blk) {
+              const int l = lb.c, lp = lb.r;
+              const int r = br.find(bl.q[l] + qn);
+              const int rp = br.find(bl.q[lp] + qnp);
+              if (r < 0 || rp < 0) continue;
+              auto kr = ps.row_of[r].find({l, n});
+              auto krp = ps.row_of[rp].find({lp, np});
+              if (kr == ps.row_of[r].end() || krp == ps.row_of[rp].end()) continue;
+              const double* Bp;
+              int ldb;
+              if (pr.z < 0) {
+                if (r != rp) continue;
+                Bp = PSI + ps.off[r] + kr->second * br.d[r];
+                ldb = br.d[r];
+              } else {
+                auto it = tloc.find({pr.z, r});
+                if (it == tloc.end()) continue;
+                const Layout::Blk* zb = plan->zops[pr.z].lay->col(r);
+                if (!zb || zb->r != rp) continue;
+                Bp = it->second.first + kr->second * it->second.second;
+                ldb = it->second.second;
+              }
+              const double sg = ((pr.ypar & 1) && (bl.q[l].n & 1)) ? -1.0 : 1.0;
+              auto ok = std::make_tuple(rp, krp->second);
+              outs[ok].push_back({pr.L.data + lb.off, Bp, lb.dc, ldb, lb.dc, 0, yv * sg});
+              out_m[ok] = lb.dr;
+            }
+          }
+      }
+    }
+    GemmBatch b2;
+    for (auto& o : outs) {
+      const int rp = std::get<0>(o.first);
+      const int64_t row = std::get<1>(o.first);
+      const size_t s0 = b2.segs.size();
+      for (auto& sgm : o.second) b2.segs.push_back(sgm);
+      b2.add_problem(SIG + ps.off[rp] + row * br.d[rp], br.d[rp], out_m[o.first], br.d[rp], s0,
+                     b2.segs.size(), 1);
+    }
+    // largest tiles first (longest segment lists)
+    std::stable_sort(b2.tiles.begin(), b2.tiles.end(), [](const GemmTile& a, const GemmTile& b) {
+      return (a.seg_end - a.seg_begin) > (b.seg_end - b.seg_begin);
+    });
+    plan->flops += b1.flops + b2.flops;
+    plan->stage1.emplace_back();
+    upload_gemm(b1, plan->stage1.back());
+    plan->stage2.emplace_back();
+    upload_gemm(b2, plan->stage2.back());
+  }
+  return plan;
+}
+
+void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, hipStream_t s) {
+  const int64_t n = plan.psi.size;
+  DMRG_HIP(hipMemcpyAsync(plan.psi_in.p, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_fill(plan.sigma_out.as<double>(), 0.0, n, s);
+  for (size_t c = 0; c < plan.stage1.size(); ++c) {
+    launch_gemm_f64(plan.stage1[c], s);
+    launch_gemm_f64(plan.stage2[c], s);
+  }
+  DMRG_HIP(hipMemcpyAsync(sigma, plan.sigma_out.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace dmrg

@@ -1,0 +1,249 @@
+// Block-sparse renormalised operators, their construction along the chain,
+// and the two-site sigma plan.
+#pragma once
+#include <map>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+#include "gemm.h"
+#include "strings.h"
+
+namespace dmrg {
+
+// ---- problem (integrals) ----------------------------------------------------
+struct Problem {
+  int K = 0, N = 0, tsz = 0;
+  double e_core = 0;
+  std::vector<double> h, eri;  // K*K and K^4, chemists' (pq|rs)
+  double t(int P, int Q) const {
+    return ((P ^ Q) & 1) ? 0.0 : h[(size_t)(P >> 1) * K + (Q >> 1)];
+  }
+};
+
+// Calls f(coef, str) for every nonzero term of
+//   H = sum t_PQ a+_P a_Q + 1/2 sum V_PQRS a+_P a+_Q a_R a_S,
+//   V_PQRS = (ps|qr) d(s_P,s_S) d(s_Q,s_R)
+// restricted to spatial-index tuples accepted by keep(list, count).
+template <class Keep, class F>
+void for_each_term(const Problem& P, Keep&& keep, F&& f) {
+  const int K = P.K;
+  for (int p = 0; p < K; ++p)
+    for (int q = 0; q < K; ++q) {
+      const int ix[2] = {p, q};
+      if (!keep(ix, 2)) continue;
+      const double t = P.h[(size_t)p * K + q];
+      if (t == 0.0) continue;
+      for (int a = 0; a < 2; ++a) {
+        Str s;
+        s.push(2 * p + a, 1);
+        s.push(2 * q + a, 0);
+        f(t, s);
+      }
+    }
+  for (int p = 0; p < K; ++p)
+    for (int q = 0; q < K; ++q)
+      for (int r = 0; r < K; ++r)
+        for (int u = 0; u < K; ++u) {
+          const int ix[4] = {p, q, r, u};
+          if (!keep(ix, 4)) continue;
+          const double g = P.eri[(((size_t)p * K + u) * K + q) * K + r];  // (pu|qr)
+          if (g == 0.0) continue;
+          for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+              const int A = 2 * p + a, B = 2 * q + b, C = 2 * r + b, D = 2 * u + a;
+              if (A == B || C == D) continue;
+              Str s;
+              s.push(A, 1);
+              s.push(B, 1);
+              s.push(C, 0);
+              s.push(D, 0);
+              f(0.5 * g, s);
+            }
+        }
+}
+
+// ---- bonds and layouts --------------------------------------------------------
+struct Bond {
+  std::vector<QN> q;
+  std::vector<int> d;
+  std::vector<int64_t> off;  // state offset of each sector
+  int64_t total = 0;
+  std::map<QN, int> idx;
+  void finish() {
+    off.assign(q.size(), 0);
+    total = 0;
+    idx.clear();
+    for (size_t k = 0; k < q.size(); ++k) {
+      off[k] = total;
+      total += d[k];
+      idx[q[k]] = (int)k;
+    }
+  }
+  int find(QN x) const {
+    auto it = idx.find(x);
+    return it == idx.end() ? -1 : it->second;
+  }
+  size_t size() const { return q.size(); }
+};
+
+// Blocks of an operator with own quantum-number change dq acting on the
+// states of one bond.  Bond labels are the quantum numbers of the part left
+// of the bond, so for a left block row = col + dq and for a right block
+// row = col - dq.
+struct Layout {
+  QN dq;
+  int side = +1;
+  struct Blk {
+    int r, c, dr, dc;
+    int64_t off;
+  };
+  std::vector<Blk> blk;
+  std::vector<int> by_col;
+  int64_t nnz = 0;
+  void build(const Bond& b, QN dq_, int side_) {
+    dq = dq_;
+    side = side_;
+    blk.clear();
+    by_col.assign(b.size(), -1);
+    nnz = 0;
+    for (size_t c = 0; c < b.size(); ++c) {
+      QN rq = side > 0 ? b.q[c] + dq : b.q[c] - dq;
+      int r = b.find(rq);
+      if (r < 0) continue;
+      by_col[c] = (int)blk.size();
+      blk.push_back({r, (int)c, b.d[r], b.d[c], nnz});
+      nnz += (int64_t)b.d[r] * b.d[c];
+    }
+  }
+  const Blk* col(int c) const { return (c >= 0 && by_col[c] >= 0) ? &blk[by_col[c]] : nullptr; }
+};
+
+// ---- operators ----------------------------------------------------------------
+enum OpKind : uint8_t { kIdent = 0, kHam = 1, kNormal = 2, kComp = 3, kPsum = 4 };
+
+struct OpKey {
+  uint8_t kind = 0;
+  uint64_t s = 0;
+  bool operator==(const OpKey& o) const { return kind == o.kind && s == o.s; }
+};
+struct OpKeyHash {
+  size_t operator()(const OpKey& k) const { return std::hash<uint64_t>()(k.s * 8 + k.kind); }
+};
+
+struct OpClass {
+  Layout L;
+  int nops = 0;
+  DevBuf data;  // nops x nnz, FP64
+  double* op(int i) const { return data.as<double>() + (int64_t)i * L.nnz; }
+};
+
+struct OpRef {
+  int cls = -1, idx = -1;
+};
+
+// A set of renormalised operators on one block.
+struct Env {
+  int side = +1;  // +1: sites [0, bond); -1: sites [bond, K)
+  int bond = 0;
+  Bond basis;
+  std::vector<std::unique_ptr<OpClass>> classes;
+  std::map<QN, int> class_of_dq;
+  std::unordered_map<OpKey, OpRef, OpKeyHash> ops;
+  int class_for(QN dq) {
+    auto it = class_of_dq.find(dq);
+    if (it != class_of_dq.end()) return it->second;
+    auto c = std::make_unique<OpClass>();
+    c->L.build(basis, dq, side);
+    classes.push_back(std::move(c));
+    class_of_dq[dq] = (int)classes.size() - 1;
+    return (int)classes.size() - 1;
+  }
+  OpRef add(OpKey k, QN dq) {
+    auto it = ops.find(k);
+    if (it != ops.end()) return it->second;
+    int c = class_for(dq);
+    OpRef r{c, classes[c]->nops++};
+    ops[k] = r;
+    return r;
+  }
+  const OpRef* get(OpKey k) const {
+    auto it = ops.find(k);
+    return it == ops.end() ? nullptr : &it->second;
+  }
+  void allocate(hipStream_t s);  // device arrays for every class, zeroed
+  size_t bytes() const {
+    size_t b = 0;
+    for (auto& c : classes) b += c->data.bytes;
+    return b;
+  }
+};
+
+// Device copy of one site tensor: blocks (l, n) -> r packed in (l, n) order.
+struct SiteTensor {
+  std::vector<int64_t> off;  // offset of block (l, n) at index 4*l+n, -1 if absent
+  DevBuf data;
+};
+
+struct Mps {
+  int K = 0, N = 0, tsz = 0;
+  std::vector<Bond> bonds;       // K+1
+  std::vector<SiteTensor> site;  // K (window sites may be empty)
+};
+
+// Builds the operators of sites [0, b+1) from those of [0, b) and site b.
+std::unique_ptr<Env> left_start(const Mps& m, hipStream_t s);
+std::unique_ptr<Env> right_start(const Mps& m, hipStream_t s);
+std::unique_ptr<Env> grow_left(const Problem& P, const Mps& m, const Env& old, DevBuf& scratch,
+                               hipStream_t s);
+std::unique_ptr<Env> grow_right(const Problem& P, const Mps& m, const Env& old, DevBuf& scratch,
+                                hipStream_t s);
+
+// ---- sigma ----------------------------------------------------------------------
+// psi of window (i, i+1) is stored right-sector-major: for each sector r of
+// bond i+2 the rows (l, n1, n2) with Q_l + Q_n1 + Q_n2 = Q_r in ascending
+// order form a dense M_r x d_r row-major matrix Psi_r; the Psi_r follow each
+// other in ascending r.
+struct PsiLayout {
+  std::vector<int64_t> rows_of;  // M_r
+  std::vector<int64_t> off;      // element offset of Psi_r
+  std::vector<std::map<std::pair<int, int>, int64_t>> row_of;  // per r: (l, 4*n1+n2) -> row
+  int64_t size = 0;
+  void build(const Bond& bl, const Bond& br);
+};
+
+struct OpView {
+  const double* data = nullptr;
+  const Layout* lay = nullptr;
+};
+
+struct SigmaPair {
+  OpView L;  // left operator (stored, or a window partial sum)
+  int z;     // index into SigmaPlan::zops, -1 = identity
+  Mat16 y;   // site matrix, coefficient folded in
+  int ypar;  // fermion parity of the site string
+};
+
+struct SigmaPlan {
+  int window = -1;
+  PsiLayout psi;
+  std::unique_ptr<Env> psums;  // window partial sums of left operators
+  std::vector<OpView> zops;    // distinct right operators
+  std::vector<int> zpar;
+  std::vector<SigmaPair> pairs;
+  DevBuf psi_in, sigma_out;    // internal copies so descriptors stay fixed
+  DevBuf ws;                   // stage-1 intermediates
+  std::vector<DevGemm> stage1, stage2;  // per chunk
+  double flops = 0;            // algorithmic FLOPs of one sigma
+  int64_t ws_doubles = 0;
+};
+
+// Plans the sigma of window (i, i+1) from the left block at bond i and the
+// right block at bond i+2 (both renormalised).
+std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env& L, const Env& R,
+                                      int64_t ws_budget_doubles, hipStream_t s);
+// sigma = H_eff psi (device pointers, right-sector-major psi layout).
+void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, hipStream_t s);
+
+}  // namespace dmrg

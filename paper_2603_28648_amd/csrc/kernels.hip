@@ -1,0 +1,269 @@
+// gfx950 kernels: FP64-MFMA grouped GEMM and FP64 BLAS-1 helpers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gemm.h"
+
+namespace dmrg {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// One workgroup (4 waves) per 64x64 output tile; each wave owns a 32x32
+// quarter as 2x2 blocks of v_mfma_f64_16x16x4f64.  Operands are staged
+// through LDS in k-slabs of 16 with bounds-checked (zero-filled) loads, so
+// ragged m, n, k need no padding in memory.  alpha is folded into A.
+//
+// MFMA operand layout (16x16x4 f64, wave64): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; accumulator element v of lane l holds D[4*v + l/16][l%16]
+// (rows interleaved across the four 16-lane groups).
+constexpr int kTK = 16;
+
+__global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ tiles,
+                                                   const GemmSeg* __restrict__ segs) {
+  __shared__ double As[kTK][kTileM + 1];
+  __shared__ double Bs[kTK][kTileN + 1];
+  const GemmTile t = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  f64x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int s = t.seg_begin; s < t.seg_end; ++s) {
+    const GemmSeg g = segs[s];
+    const double* __restrict__ A = static_cast<const double*>(g.a);
+    const double* __restrict__ B = static_cast<const double*>(g.b);
+    const bool ta = g.flags & kTransA, tb = g.flags & kTransB;
+    const double al = g.alpha;
+    for (int k0 = 0; k0 < g.k; k0 += kTK) {
+#pragma unroll
+      for (int r = 0; r < (kTileM * kTK) / 256; ++r) {
+        const int e = r * 256 + tid;
+        int i, kk;
+        if (!ta) { i = e / kTK; kk = e % kTK; }
+        else { kk = e / kTileM; i = e % kTileM; }
+        const int gk = k0 + kk;
+        double v = 0.0;
+        if (i < t.m && gk < g.k) {
+          const int64_t gi = (int64_t)t.row0 + i;
+          v = ta ? A[(int64_t)gk * g.lda + gi] : A[gi * g.lda + gk];
+        }
+        As[kk][i] = v * al;
+      }
+#pragma unroll
+      for (int r = 0; r < (kTileN * kTK) / 256; ++r) {
+        const int e = r * 256 + tid;
+        int j, kk;
+        if (!tb) { kk = e / kTileN; j = e % kTileN; }
+        else { j = e / kTK; kk = e % kTK; }
+        const int gk = k0 + kk;
+        double v = 0.0;
+        if (j < t.n && gk < g.k) {
+          const int64_t gj = (int64_t)t.col0 + j;
+          v = tb ? B[gj * g.ldb + gk] : B[(int64_t)gk * g.ldb + gj];
+        }
+        Bs[kk][j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kTK; kk += 4) {
+        const double a0 = As[kk + lk][wm + lr];
+        const double a1 = As[kk + lk][wm + 16 + lr];
+        const double b0 = Bs[kk + lk][wn + lr];
+        const double b1 = Bs[kk + lk][wn + 16 + lr];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  double* __restrict__ C = static_cast<double*>(t.c);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wm + bi * 16 + 4 * v + lk;
+        const int j = wn + bj * 16 + lr;
+        if (i < t.m && j < t.n) {
+          double* p = C + ((int64_t)t.row0 + i) * t.ldc + (t.col0 + j);
+          const double val = acc[bi][bj][v];
+          *p = t.beta ? (*p + val) : val;
+        }
+      }
+}
+
+void launch_gemm_f64(const GemmBatch& b, DevBuf& scratch, hipStream_t stream) {
+  if (b.tiles.empty()) return;
+  const size_t sb = b.segs.size() * sizeof(GemmSeg);
+  const size_t tb = b.tiles.size() * sizeof(GemmTile);
+  const size_t need = sb + tb + 256;
+  if (scratch.bytes < need) {
+    DMRG_HIP(hipStreamSynchronize(stream));
+    scratch.alloc(need);
+  }
+  char* base = scratch.as<char>();
+  GemmSeg* dsegs = reinterpret_cast<GemmSeg*>(base);
+  GemmTile* dtiles = reinterpret_cast<GemmTile*>(base + ((sb + 255) / 256) * 256);
+  DMRG_HIP(hipMemcpyAsync(dsegs, b.segs.data(), sb, hipMemcpyHostToDevice, stream));
+  DMRG_HIP(hipMemcpyAsync(dtiles, b.tiles.data(), tb, hipMemcpyHostToDevice, stream));
+  const size_t nt = b.tiles.size();
+  for (size_t off = 0; off < nt; off += (size_t)1 << 30) {
+    const unsigned cnt = (unsigned)std::min<size_t>(nt - off, (size_t)1 << 30);
+    hipLaunchKernelGGL(k_gemm_f64, dim3(cnt), dim3(256), 0, stream, dtiles + off, dsegs);
+  }
+  DMRG_HIP(hipGetLastError());
+  // descriptors come from pageable host memory: make sure the copies are done
+  // before the caller may release or reuse the host vectors
+  DMRG_HIP(hipStreamSynchronize(stream));
+}
+
+void upload_gemm(const GemmBatch& b, DevGemm& d) {
+  const size_t sb = b.segs.size() * sizeof(GemmSeg);
+  const size_t tb = b.tiles.size() * sizeof(GemmTile);
+  const size_t sba = ((sb + 255) / 256) * 256;
+  d.buf.alloc(sba + tb + 256);
+  d.segs = reinterpret_cast<GemmSeg*>(d.buf.as<char>());
+  d.tiles = reinterpret_cast<GemmTile*>(d.buf.as<char>() + sba);
+  if (sb) DMRG_HIP(hipMemcpy(d.segs, b.segs.data(), sb, hipMemcpyHostToDevice));
+  if (tb) DMRG_HIP(hipMemcpy(d.tiles, b.tiles.data(), tb, hipMemcpyHostToDevice));
+  d.ntiles = b.tiles.size();
+  d.nsegs = b.segs.size();
+  d.flops = b.flops;
+}
+
+void launch_gemm_f64(const DevGemm& d, hipStream_t stream) {
+  for (size_t off = 0; off < d.ntiles; off += (size_t)1 << 30) {
+    const unsigned cnt = (unsigned)std::min<size_t>(d.ntiles - off, (size_t)1 << 30);
+    hipLaunchKernelGGL(k_gemm_f64, dim3(cnt), dim3(256), 0, stream, d.tiles + off, d.segs);
+  }
+  DMRG_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_scale(double* x, double a, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] *= a;
+}
+__global__ void k_axpy(double* y, double a, const double* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+__global__ void k_fill(double* x, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+}
+
+void launch_scale(double* x, double a, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(256), 0, s, x, a, n);
+  DMRG_HIP(hipGetLastError());
+}
+void launch_axpy(double* y, double a, const double* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, y, a, x, n);
+  DMRG_HIP(hipGetLastError());
+}
+void launch_fill(double* x, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(256), 0, s, x, v, n);
+  DMRG_HIP(hipGetLastError());
+}
+
+// Deterministic two-pass dot products: block partials, then one block per row.
+constexpr int kDotBlocks = 512;
+__global__ __launch_bounds__(256) void k_multidot_partial(double* part, const double* X,
+                                                          int64_t ldx, const double* y,
+                                                          int64_t n) {
+  __shared__ double red[256];
+  const int j = blockIdx.y;
+  const double* x = X + j * ldx;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += x[i] * y[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)j * gridDim.x + blockIdx.x] = red[0];
+}
+__global__ __launch_bounds__(256) void k_reduce_rows(double* out, const double* part, int nb) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[(int64_t)j * nb + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+void launch_multidot(double* out, const double* X, int64_t ldx, int nv, const double* y,
+                     int64_t n, hipStream_t s) {
+  if (nv <= 0) return;
+  static thread_local DevBuf part;
+  const size_t need = (size_t)nv * kDotBlocks * sizeof(double);
+  if (part.bytes < need) {
+    DMRG_HIP(hipStreamSynchronize(s));
+    part.alloc(need);
+  }
+  int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (n + 255) / 256));
+  hipLaunchKernelGGL(k_multidot_partial, dim3(nb, nv), dim3(256), 0, s, part.as<double>(), X,
+                     ldx, y, n);
+  hipLaunchKernelGGL(k_reduce_rows, dim3(nv), dim3(256), 0, s, out, part.as<double>(), nb);
+  DMRG_HIP(hipGetLastError());
+}
+
+__global__ void k_lincomb(double* y, const double* X, int64_t ldx, int nv, const double* c,
+                          int64_t n, double beta) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double acc = beta == 0.0 ? 0.0 : beta * y[i];
+    for (int j = 0; j < nv; ++j) acc += c[j] * X[j * ldx + i];
+    y[i] = acc;
+  }
+}
+void launch_lincomb(double* y, const double* X, int64_t ldx, int nv, const double* c,
+                    int64_t n, double beta, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n)), dim3(256), 0, s, y, X, ldx, nv, c, n, beta);
+  DMRG_HIP(hipGetLastError());
+}
+
+__global__ void k_row_scatter_add(double* dst, const double* src, const int64_t* off, int64_t n) {
+  const int r = blockIdx.y;
+  double* d = dst + off[r];
+  const double* x = src + (int64_t)r * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] += x[i];
+}
+void launch_row_scatter_add(double* dst, const double* src, const int64_t* dst_off, int nrows,
+                            int64_t n, hipStream_t s) {
+  if (nrows <= 0 || n <= 0) return;
+  unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 64));
+  hipLaunchKernelGGL(k_row_scatter_add, dim3(gx, nrows), dim3(256), 0, s, dst, src, dst_off, n);
+  DMRG_HIP(hipGetLastError());
+}
+
+}  // namespace dmrg

@@ -1,0 +1,74 @@
+"""FP64 sigma of the HIP library against the CPU oracle (GPU).
+
+Small windows are checked against the plain definition P^T H P psi
+(oracle.projection); larger ones against the oracle's block-sparse
+normal/complementary sigma, which is itself pinned to the definition on the
+CPU.  Bar: ||d sigma|| / ||sigma|| <= 1e-10 and every element within
+1e-10 * max|sigma| (FP64 arithmetic, rounding only).
+"""
+import numpy as np
+import pytest
+
+from tests.helpers import case, lib_sigma, rel_err, max_abs, lib_load, lib_sigma_flat
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+SMALL = [  # K, N, 2Sz, D, window
+    (2, 2, 0, 16, 0),
+    (4, 4, 0, 100, 0), (4, 4, 0, 100, 1), (4, 4, 0, 100, 2),
+    (5, 5, 1, 8, 1), (5, 4, -2, 12, 3),
+    (6, 6, 0, 12, 2), (6, 5, 1, 10, 0), (6, 7, -1, 10, 4), (6, 6, 2, 12, 3),
+    (8, 8, 0, 64, 3), (8, 8, 0, 20, 1), (8, 6, 2, 30, 5),
+]
+
+
+@pytest.mark.parametrize("K,N,tsz,D,i", SMALL)
+def test_sigma_matches_projection(ctx, K, N, tsz, D, i):
+    from oracle.projection import ProjectedHamiltonian
+    print(f"sigma vs P^T H P: K={K} N={N} 2Sz={tsz} D={D} window={i}", flush=True)
+    h, eri, m = case(K, N, tsz, D, i)
+    ref = ProjectedHamiltonian(m, h, eri).apply(m.psi)
+    got = lib_sigma(ctx, h, eri, m)
+    scale = max(float(np.max(np.abs(v))) for v in ref.values())
+    assert rel_err(got, ref) <= TOL
+    assert max_abs(got, ref) <= TOL * scale
+
+
+MID = [(12, 12, 0, 256, 5), (10, 9, 1, 200, 2), (12, 14, 2, 150, 7)]
+
+
+@pytest.mark.parametrize("K,N,tsz,D,i", MID)
+def test_sigma_matches_blocksparse_oracle(ctx, K, N, tsz, D, i):
+    from oracle.blocksparse import BlockSparseSigma
+    print(f"sigma vs block-sparse oracle: K={K} N={N} 2Sz={tsz} D={D} window={i}", flush=True)
+    h, eri, m = case(K, N, tsz, D, i)
+    ref = BlockSparseSigma(m, h, eri).apply(m.psi)
+    got = lib_sigma(ctx, h, eri, m)
+    scale = max(float(np.max(np.abs(v))) for v in ref.values())
+    assert rel_err(got, ref) <= TOL
+    assert max_abs(got, ref) <= TOL * scale
+
+
+def test_sigma_is_symmetric_and_linear(ctx):
+    """<x|H y> = <H x|y> and H(a x + y) = a Hx + Hy at a mid size."""
+    print("sigma symmetry/linearity K=12 D=256", flush=True)
+    h, eri, m = case(12, 12, 0, 256, 5)
+    n = lib_load(ctx, h, eri, m)
+    rng = np.random.default_rng(3)
+    x, y = rng.normal(size=n), rng.normal(size=n)
+    hx, hy = lib_sigma_flat(ctx, x), lib_sigma_flat(ctx, y)
+    h2 = lib_sigma_flat(ctx, 0.3 * x + y)
+    s = np.linalg.norm(hx) * np.linalg.norm(y)
+    assert abs(x @ hy - hx @ y) <= 1e-12 * s
+    assert np.linalg.norm(h2 - (0.3 * hx + hy)) <= 1e-12 * np.linalg.norm(h2)
+
+
+def test_sigma_repeat_is_bitwise_deterministic(ctx):
+    print("sigma determinism K=10 D=200", flush=True)
+    h, eri, m = case(10, 9, 1, 200, 2)
+    n = lib_load(ctx, h, eri, m)
+    x = np.random.default_rng(4).normal(size=n)
+    a, b = lib_sigma_flat(ctx, x), lib_sigma_flat(ctx, x)
+    assert np.array_equal(a, b)
