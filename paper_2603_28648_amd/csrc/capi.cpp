@@ -1,5 +1,6 @@
 // C ABI of the library (see include/dmrg.h).  Arguments are validated on the
 // host before any device work; exceptions never cross the ABI.
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -25,6 +26,16 @@ struct dmrg_ctx_s {
 };
 
 static thread_local std::string g_err;
+
+// DMRG_VERBOSE=1 prints one line per renormalisation step to stderr.
+static bool verbose() {
+  static int v = -1;
+  if (v < 0) v = std::getenv("DMRG_VERBOSE") ? std::atoi(std::getenv("DMRG_VERBOSE")) : 0;
+  return v > 0;
+}
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 
 static dmrg_status fail(dmrg_ctx c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -177,7 +188,13 @@ dmrg_status dmrg_build_ops(dmrg_ctx c, const dmrg_problem* problem, const dmrg_m
       while (b > 0 && !c->left.count(b)) --b;
       std::unique_ptr<Env> cur = c->left.count(b) ? std::move(c->left[b]) : left_start(c->m, s);
       c->left.erase(b);
-      for (; b < site; ++b) cur = grow_left(c->P, c->m, *cur, c->desc, s);
+      for (; b < site; ++b) {
+        const double t0 = now_s();
+        cur = grow_left(c->P, c->m, *cur, c->desc, s);
+        if (verbose())
+          fprintf(stderr, "[dmrg] left block -> bond %d: %.2f s, %.2f GB\n", b + 1, now_s() - t0,
+                  cur->bytes() / 1e9), fflush(stderr);
+      }
       c->left[site] = std::move(cur);
     }
     if (!c->right.count(site + 2)) {
@@ -185,7 +202,13 @@ dmrg_status dmrg_build_ops(dmrg_ctx c, const dmrg_problem* problem, const dmrg_m
       while (b < K && !c->right.count(b)) ++b;
       std::unique_ptr<Env> cur = c->right.count(b) ? std::move(c->right[b]) : right_start(c->m, s);
       c->right.erase(b);
-      for (; b > site + 2; --b) cur = grow_right(c->P, c->m, *cur, c->desc, s);
+      for (; b > site + 2; --b) {
+        const double t0 = now_s();
+        cur = grow_right(c->P, c->m, *cur, c->desc, s);
+        if (verbose())
+          fprintf(stderr, "[dmrg] right block -> bond %d: %.2f s, %.2f GB\n", b - 1, now_s() - t0,
+                  cur->bytes() / 1e9), fflush(stderr);
+      }
       c->right[site + 2] = std::move(cur);
     }
     // keep only the blocks that bracket this window
@@ -193,8 +216,13 @@ dmrg_status dmrg_build_ops(dmrg_ctx c, const dmrg_problem* problem, const dmrg_m
       it = (it->first != site) ? c->left.erase(it) : std::next(it);
     for (auto it = c->right.begin(); it != c->right.end();)
       it = (it->first != site + 2) ? c->right.erase(it) : std::next(it);
+    const double t0 = now_s();
     c->plan = plan_sigma(c->P, c->m, *c->left[site], *c->right[site + 2], c->ws_budget, s);
     DMRG_HIP(hipStreamSynchronize(s));
+    if (verbose())
+      fprintf(stderr, "[dmrg] sigma plan: %.2f s, %zu pairs, %zu right ops, %.3e flops\n",
+              now_s() - t0, c->plan->pairs.size(), c->plan->zops.size(), c->plan->flops),
+          fflush(stderr);
     (void)precision_mask;
     return kOk;
   });
