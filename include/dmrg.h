@@ -128,8 +128,42 @@ typedef struct {
   int64_t operator_bytes; /* device bytes of the left + right block operators */
   int32_t n_chunks;
   int32_t pad;
+  double flops_stage1;   /* psi x right operators */
+  double flops_stage2;   /* left operators x stage-1 results */
 } dmrg_sigma_info;
 dmrg_status dmrg_sigma_get_info(dmrg_ctx ctx, int32_t precision, dmrg_sigma_info* out);
+
+/* Davidson solve for the lowest eigenpair of H_eff at the current window
+ * (Davidson 1975, diagonal preconditioner, thick restart to the Ritz vector;
+ * the Numerical-procedure section's eigensolver tolerance is a residual
+ * norm, here ||H_eff u - theta u||_2 with ||u||_2 = 1).  Sigma products run
+ * through a precision ladder: stage s uses ladder[s] until the residual is
+ * below ladder_tol[s] or stalls, then the subspace restarts from the Ritz
+ * vector; the last stage must be DMRG_FP64 and runs to tol.  Orthogonalisation
+ * and the subspace matrices are FP64.  energy_out = FP64 Rayleigh quotient
+ * + e_core.  psi_inout: start vector in, normalised Ritz vector out.
+ * Returns DMRG_WARN_NOT_CONVERGED (with the best vector and energy) when
+ * max_iter corrections were not enough. */
+typedef struct {
+  int32_t max_iter;      /* correction vectors (default 100) */
+  int32_t max_subspace;  /* 3..64 (default 24) */
+  double tol;            /* default 1e-6 */
+  int32_t n_ladder;      /* 1..4 */
+  int32_t ladder[4];     /* DMRG_FP64 / DMRG_BF16 / DMRG_BF16X3 per stage */
+  double ladder_tol[4];  /* stage-end residuals (all stages but the last) */
+} dmrg_davidson_opts;
+
+typedef struct {
+  double energy, residual, time_ms, sigma_ms;
+  int32_t iterations, converged;
+  int32_t n_sigma[3];    /* sigma products per precision */
+  int32_t n_history;     /* entries used below (<= 256) */
+  double residual_history[256];
+  int32_t stage_history[256];
+} dmrg_davidson_stats;
+
+dmrg_status dmrg_davidson(dmrg_ctx ctx, double* psi_inout, const dmrg_davidson_opts* opts,
+                          double* energy_out, dmrg_davidson_stats* stats_out);
 
 /* Diagnostic: C = alpha * op(A) op(B) + beta * C with the library's grouped
  * GEMM kernel of the given precision, for kernel-level numerics tests.

@@ -49,7 +49,23 @@ class SigmaInfo(ctypes.Structure):
                 ("n_stage1_tiles", ctypes.c_int64), ("n_stage2_tiles", ctypes.c_int64),
                 ("n_stage2_segments", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("operator_bytes", ctypes.c_int64), ("n_chunks", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("pad", ctypes.c_int32), ("flops_stage1", ctypes.c_double),
+                ("flops_stage2", ctypes.c_double)]
+
+
+class DavidsonOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("max_subspace", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("n_ladder", ctypes.c_int32),
+                ("ladder", ctypes.c_int32 * 4), ("ladder_tol", ctypes.c_double * 4)]
+
+
+class DavidsonStats(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_double), ("residual", ctypes.c_double),
+                ("time_ms", ctypes.c_double), ("sigma_ms", ctypes.c_double),
+                ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("n_sigma", ctypes.c_int32 * 3), ("n_history", ctypes.c_int32),
+                ("residual_history", ctypes.c_double * 256),
+                ("stage_history", ctypes.c_int32 * 256)]
 
 
 EXPORTS = {
@@ -61,6 +77,8 @@ EXPORTS = {
     "dmrg_psi_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "dmrg_sigma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "dmrg_sigma_get_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SigmaInfo)]),
+    "dmrg_davidson": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(DavidsonOpts),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(DavidsonStats)]),
     "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -168,6 +186,31 @@ class Context:
         p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self._check(self.lib.dmrg_sigma(self.h, _dev_ptr(psi), _dev_ptr(out), p), self.h)
         return out
+
+    def davidson(self, psi, tol=1e-6, max_iter=100, max_subspace=24,
+                 ladder=(("fp64", None),)):
+        """Lowest eigenpair at the current window; psi (device) is updated in place.
+
+        ladder: sequence of (precision, stage-end residual); the last stage
+        must be fp64 (its threshold is tol)."""
+        o = DavidsonOpts()
+        o.max_iter, o.max_subspace, o.tol = int(max_iter), int(max_subspace), float(tol)
+        o.n_ladder = len(ladder)
+        for k, (p, t) in enumerate(ladder):
+            o.ladder[k] = PRECISIONS[p] if isinstance(p, str) else int(p)
+            o.ladder_tol[k] = float(t) if t is not None else 0.0
+        e = ctypes.c_double()
+        st = DavidsonStats()
+        status = self.lib.dmrg_davidson(self.h, _dev_ptr(psi), ctypes.byref(o), ctypes.byref(e),
+                                        ctypes.byref(st))
+        self._check(status, self.h)
+        n = st.n_history
+        return {"energy": e.value, "residual": st.residual, "time_ms": st.time_ms,
+                "sigma_ms": st.sigma_ms, "iterations": st.iterations,
+                "converged": bool(st.converged), "status": status,
+                "n_sigma": {"fp64": st.n_sigma[0], "bf16": st.n_sigma[1], "bf16x3": st.n_sigma[2]},
+                "residual_history": list(st.residual_history[:n]),
+                "stage_history": list(st.stage_history[:n])}
 
     def debug_gemm(self, a, b, c, trans_a=False, trans_b=False, alpha=1.0, beta=0,
                    precision="fp64"):

@@ -18,7 +18,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdmrg_mi355x.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "engine.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "kernels_bf16.hip", "engine.cpp", "davidson.cpp", "capi.cpp"]
 ARCH = "gfx950"
 
 

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/dmrg.h"
+#include "davidson.h"
 #include "engine.h"
 
 using namespace dmrg;
@@ -241,9 +242,57 @@ dmrg_status dmrg_sigma(dmrg_ctx c, const double* psi, double* sigma, int32_t pre
     DMRG_REQUIRE(c->plan, kErrState, "sigma: call dmrg_build_ops first");
     DMRG_REQUIRE(psi && sigma, kErrInvalidArg, "sigma: NULL buffer");
     DMRG_REQUIRE(precision >= 0 && precision <= 2, kErrInvalidArg, "sigma: unknown precision");
-    if (precision != DMRG_FP64) throw Error(kErrUnimplemented, "sigma: only DMRG_FP64 is available");
-    run_sigma(*c->plan, psi, sigma, c->stream);
+    run_sigma(*c->plan, psi, sigma, precision, c->stream);
     return kOk;
+  });
+}
+
+dmrg_status dmrg_davidson(dmrg_ctx c, double* psi, const dmrg_davidson_opts* opts,
+                          double* energy_out, dmrg_davidson_stats* stats) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->plan, kErrState, "davidson: call dmrg_build_ops first");
+    DMRG_REQUIRE(psi && opts && energy_out, kErrInvalidArg, "davidson: NULL argument");
+    DavidsonOpts o;
+    o.max_iter = opts->max_iter;
+    o.max_subspace = opts->max_subspace;
+    o.tol = opts->tol;
+    o.n_ladder = opts->n_ladder;
+    DMRG_REQUIRE(o.max_iter >= 0 && o.max_subspace >= 3 && o.max_subspace <= 64, kErrInvalidArg,
+                 "davidson: need max_iter >= 0 and 3 <= max_subspace <= 64");
+    DMRG_REQUIRE(o.tol > 0, kErrInvalidArg, "davidson: tol must be positive");
+    DMRG_REQUIRE(o.n_ladder >= 1 && o.n_ladder <= 4, kErrInvalidArg, "davidson: 1 <= n_ladder <= 4");
+    for (int k = 0; k < o.n_ladder; ++k) {
+      DMRG_REQUIRE(opts->ladder[k] >= 0 && opts->ladder[k] <= 2, kErrInvalidArg, "davidson: bad ladder precision");
+      o.ladder[k] = opts->ladder[k];
+      o.ladder_tol[k] = opts->ladder_tol[k];
+    }
+    DMRG_REQUIRE(o.ladder[o.n_ladder - 1] == DMRG_FP64, kErrInvalidArg, "davidson: the last ladder stage must be DMRG_FP64");
+    SigmaPlan& p = *c->plan;
+    if (!p.diag_ready) {
+      build_diagonal(p, c->m.bonds[c->window], c->m.bonds[c->window + 2], c->stream);
+      p.diag_ready = true;
+    }
+    DavidsonResult r;
+    const int st = davidson(p, psi, o, r, c->stream);
+    *energy_out = r.energy + c->P.e_core;
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->energy = r.energy + c->P.e_core;
+      stats->residual = r.residual;
+      stats->time_ms = r.time_ms;
+      stats->sigma_ms = r.sigma_ms;
+      stats->iterations = r.iterations;
+      stats->converged = r.converged;
+      for (int k = 0; k < 3; ++k) stats->n_sigma[k] = r.n_sigma[k];
+      const int nh = (int)std::min<size_t>(256, r.residual_history.size());
+      stats->n_history = nh;
+      for (int k = 0; k < nh; ++k) {
+        stats->residual_history[k] = r.residual_history[k];
+        stats->stage_history[k] = r.stage_history[k];
+      }
+    }
+    return st;
   });
 }
 
@@ -253,16 +302,18 @@ dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* 
   std::memset(out, 0, sizeof(*out));
   const SigmaPlan& p = *c->plan;
   out->flops = p.flops;
+  out->flops_stage1 = p.flops_stage1;
+  out->flops_stage2 = p.flops_stage2;
   out->hw_flops = precision == DMRG_BF16X3 ? 3 * p.flops : p.flops;
   out->n_pairs = (int64_t)p.pairs.size();
   out->n_right_ops = (int64_t)p.zops.size();
-  for (auto& g : p.stage1) out->n_stage1_tiles += (int64_t)g.ntiles;
-  for (auto& g : p.stage2) {
+  for (auto& g : p.f64_s1) out->n_stage1_tiles += (int64_t)g.ntiles;
+  for (auto& g : p.f64_s2) {
     out->n_stage2_tiles += (int64_t)g.ntiles;
     out->n_stage2_segments += (int64_t)g.nsegs;
   }
   out->workspace_bytes = p.ws_doubles * 8;
-  out->n_chunks = (int32_t)p.stage1.size();
+  out->n_chunks = (int32_t)p.s1.size();
   for (auto& kv : c->left) out->operator_bytes += (int64_t)kv.second->bytes();
   for (auto& kv : c->right) out->operator_bytes += (int64_t)kv.second->bytes();
   if (p.psums) out->operator_bytes += (int64_t)p.psums->bytes();
@@ -280,11 +331,27 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const d
     DMRG_REQUIRE(beta == 0 || beta == 1, kErrInvalidArg, "debug_gemm: beta must be 0 or 1");
     DMRG_REQUIRE(lda >= (trans_a ? m : k) && ldb >= (trans_b ? k : n) && ldc >= n, kErrInvalidArg,
                  "debug_gemm: leading dimension too small");
-    DMRG_REQUIRE(precision == DMRG_FP64, kErrUnimplemented, "debug_gemm: only DMRG_FP64 is available");
-    GemmBatch bt;
-    bt.segs.push_back({a, b, lda, ldb, k, (trans_a ? kTransA : 0) | (trans_b ? kTransB : 0), alpha});
-    bt.add_problem(cc, ldc, m, n, 0, 1, beta);
-    launch_gemm_f64(bt, c->desc, c->stream);
+    DMRG_REQUIRE(precision >= 0 && precision <= 2, kErrInvalidArg, "debug_gemm: unknown precision");
+    const int flags = (trans_a ? kTransA : 0) | (trans_b ? kTransB : 0);
+    if (precision == DMRG_FP64) {
+      GemmBatch bt;
+      bt.segs.push_back({a, b, lda, ldb, k, flags, alpha});
+      bt.add_problem(cc, ldc, m, n, 0, 1, beta);
+      launch_gemm_f64(bt, c->desc, c->stream);
+      return kOk;
+    }
+    // BF16 copies (hi then lo) of the operand storage
+    const int64_t na = (int64_t)(trans_a ? k : m) * lda, nb = (int64_t)(trans_b ? n : k) * ldb;
+    DevBuf abf((size_t)2 * na * sizeof(uint16_t)), bbf((size_t)2 * nb * sizeof(uint16_t));
+    launch_split_bf16(abf.as<uint16_t>(), a, na, c->stream);
+    launch_split_bf16(bbf.as<uint16_t>(), b, nb, c->stream);
+    GemmBatchB bt;
+    bt.segs.push_back({abf.as<uint16_t>(), bbf.as<uint16_t>(), na, nb, lda, ldb, k, flags, alpha});
+    bt.add_problem(cc, 0, ldc, m, n, 0, 1, beta);
+    DevGemmB d;
+    upload_gemm_bf16(bt, d);
+    launch_gemm_bf16(d, precision == DMRG_BF16X3, kOutF64, 0, c->stream);
+    DMRG_HIP(hipStreamSynchronize(c->stream));
     return kOk;
   });
 }

@@ -1,0 +1,295 @@
+// Davidson eigensolver for the lowest eigenpair of H_eff (Davidson 1975) with
+// the diagonal preconditioner and a precision ladder for the sigma products.
+//
+// Vectors live on the device in FP64; the subspace matrices (k <= 64) are
+// copied to the host and diagonalised by cyclic Jacobi.  Each ladder stage
+// uses one sigma precision until the residual norm drops below the stage
+// threshold (or stalls); the subspace is then restarted from the current Ritz
+// vector with sigma recomputed in the next precision.  The last stage is
+// FP64, and the returned energy is the FP64 Rayleigh quotient.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "davidson.h"
+
+namespace dmrg {
+
+void launch_extract_diag(const DiagTask* tasks, int ntasks, hipStream_t s);
+void launch_heff_diag(double* out, int64_t rows, int dr, const int64_t* rowinfo, int64_t offR,
+                      int npairs, const double* yd, const double* Ld, int64_t DL,
+                      const double* Zd, int64_t DR, hipStream_t s);
+void launch_precondition(double* t, const double* r, const double* d, double theta, int64_t n,
+                         hipStream_t s);
+
+// ---- diagonal of H_eff (a sum over pairs with diagonal blocks) ------------
+void build_diagonal(SigmaPlan& plan, const Bond& bl, const Bond& br, hipStream_t s) {
+  const PsiLayout& ps = plan.psi;
+  std::vector<int> use;
+  for (size_t k = 0; k < plan.pairs.size(); ++k) {
+    const SigmaPair& p = plan.pairs[k];
+    if (!(p.L.lay->dq == QN{0, 0})) continue;
+    if (p.z >= 0 && !(plan.zops[p.z].lay->dq == QN{0, 0})) continue;
+    bool any = false;
+    for (int n = 0; n < 16; ++n) any = any || p.y.m[n][n] != 0;
+    if (any) use.push_back((int)k);
+  }
+  const int P = (int)use.size();
+  const int64_t DL = bl.total, DR = br.total;
+  DevBuf yd((size_t)std::max(1, P) * 16 * sizeof(double));
+  DevBuf Ld((size_t)std::max<int64_t>(1, (int64_t)P * DL) * sizeof(double));
+  DevBuf Zd((size_t)std::max<int64_t>(1, (int64_t)P * DR) * sizeof(double));
+  launch_fill(Ld.as<double>(), 0.0, (int64_t)P * DL, s);
+  launch_fill(Zd.as<double>(), 0.0, (int64_t)P * DR, s);
+  std::vector<double> hy((size_t)P * 16);
+  std::vector<DiagTask> tasks;
+  for (int q = 0; q < P; ++q) {
+    const SigmaPair& p = plan.pairs[use[q]];
+    for (int n = 0; n < 16; ++n) hy[(size_t)q * 16 + n] = p.y.m[n][n];
+    for (auto& b : p.L.lay->blk)
+      if (b.r == b.c) tasks.push_back({p.L.data + b.off, Ld.as<double>() + (int64_t)q * DL + bl.off[b.c], b.dc, 0});
+    if (p.z >= 0) {
+      for (auto& b : plan.zops[p.z].lay->blk)
+        if (b.r == b.c) tasks.push_back({plan.zops[p.z].data + b.off, Zd.as<double>() + (int64_t)q * DR + br.off[b.c], b.dc, 0});
+    } else {
+      launch_fill(Zd.as<double>() + (int64_t)q * DR, 1.0, DR, s);
+    }
+  }
+  DMRG_HIP(hipMemcpy(yd.p, hy.data(), hy.size() * sizeof(double), hipMemcpyHostToDevice));
+  DevBuf dt((size_t)std::max<size_t>(1, tasks.size()) * sizeof(DiagTask));
+  DMRG_HIP(hipMemcpy(dt.p, tasks.data(), tasks.size() * sizeof(DiagTask), hipMemcpyHostToDevice));
+  launch_extract_diag(dt.as<DiagTask>(), (int)tasks.size(), s);
+  // row info: (global left state, site index n) of every psi row
+  std::vector<int64_t> rowinfo;
+  std::vector<int64_t> rowbase(br.size(), 0);
+  for (size_t r = 0; r < br.size(); ++r) {
+    rowbase[r] = (int64_t)rowinfo.size();
+    std::vector<int64_t> rows(ps.rows_of[r] * 2, 0);
+    for (auto& kv : ps.row_of[r]) {
+      const int l = kv.first.first, n = kv.first.second;
+      for (int a = 0; a < bl.d[l]; ++a) {
+        rows[2 * (kv.second + a)] = bl.off[l] + a;
+        rows[2 * (kv.second + a) + 1] = n;
+      }
+    }
+    rowinfo.insert(rowinfo.end(), rows.begin(), rows.end());
+  }
+  DevBuf ri((size_t)std::max<size_t>(1, rowinfo.size()) * sizeof(int64_t));
+  DMRG_HIP(hipMemcpy(ri.p, rowinfo.data(), rowinfo.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  plan.diag.alloc((size_t)std::max<int64_t>(1, ps.size) * sizeof(double));
+  for (size_t r = 0; r < br.size(); ++r) {
+    if (ps.rows_of[r] == 0) continue;
+    launch_heff_diag(plan.diag.as<double>() + ps.off[r], ps.rows_of[r], br.d[r],
+                     ri.as<int64_t>() + rowbase[r], br.off[r], P, yd.as<double>(),
+                     Ld.as<double>(), DL, Zd.as<double>(), DR, s);
+  }
+  DMRG_HIP(hipStreamSynchronize(s));
+}
+
+// ---- small dense symmetric eigensolver (cyclic Jacobi) ---------------------
+static void jacobi_eigh(int n, std::vector<double> A, std::vector<double>& w,
+                        std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0, tot = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        if (i != j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+      }
+    if (off <= 1e-30 * std::max(tot, 1e-300)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (std::abs(apq) < 1e-300) continue;
+        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        const double tau = (aqq - app) / (2 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::abs(tau) + std::sqrt(1 + tau * tau));
+        const double c = 1 / std::sqrt(1 + t * t), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = c * akp - s * akq;
+          A[(size_t)k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = c * apk - s * aqk;
+          A[(size_t)q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - s * vkq;
+          V[(size_t)k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
+}
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult& res,
+             hipStream_t s) {
+  const int64_t n = plan.psi.size;
+  DMRG_REQUIRE(n > 0, kErrShape, "davidson: empty window");
+  const int kmax = std::max(3, std::min(o.max_subspace, 64));
+  const double t_start = now_ms();
+  res = DavidsonResult();
+  DevBuf Vb((size_t)kmax * n * sizeof(double)), Wb((size_t)kmax * n * sizeof(double));
+  DevBuf ub(n * sizeof(double)), wb(n * sizeof(double)), rb(n * sizeof(double)),
+      tb(n * sizeof(double)), hb(64 * sizeof(double)), cb(128 * sizeof(double));
+  double *V = Vb.as<double>(), *W = Wb.as<double>(), *u = ub.as<double>(), *w = wb.as<double>(),
+         *r = rb.as<double>(), *t = tb.as<double>(), *h = hb.as<double>(), *cc = cb.as<double>();
+  const double* d = plan.diag.as<double>();
+  std::vector<double> G((size_t)kmax * kmax, 0.0), hh(64);
+  DevBuf tmpV, tmpW;
+  std::vector<double> ev, Y;
+  auto dot = [&](const double* a, const double* b) {
+    launch_multidot(h, a, 0, 1, b, n, s);
+    double x;
+    DMRG_HIP(hipMemcpyAsync(&x, h, sizeof(double), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    return x;
+  };
+  auto sigma = [&](const double* x, double* y, int prec) {
+    const double t0 = now_ms();
+    run_sigma(plan, x, y, prec, s);
+    DMRG_HIP(hipStreamSynchronize(s));
+    res.sigma_ms += now_ms() - t0;
+    res.n_sigma[prec]++;
+  };
+  // column j of G against all previous basis vectors: G[i][j] = V_i . W_j
+  auto fill_col = [&](int k) {
+    launch_multidot(h, V, n, k + 1, W + (int64_t)k * n, n, s);
+    DMRG_HIP(hipMemcpyAsync(hh.data(), h, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i <= k; ++i) G[(size_t)i * kmax + k] = G[(size_t)k * kmax + i] = hh[i];
+  };
+  // start: V0 = psi / |psi|
+  const double nrm = std::sqrt(dot(psi, psi));
+  DMRG_REQUIRE(nrm > 0 && std::isfinite(nrm), kErrInvalidArg, "davidson: psi has zero or non-finite norm");
+  DMRG_HIP(hipMemcpyAsync(V, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_scale(V, 1.0 / nrm, n, s);
+  int stage = 0;
+  const int nst = std::max(1, o.n_ladder);
+  auto prec_of = [&](int st) { return o.n_ladder > 0 ? o.ladder[st] : 0; };
+  sigma(V, W, prec_of(stage));
+  int k = 1;
+  fill_col(0);
+  double theta = G[0], rnorm = 1e300;
+  std::vector<double> hist;
+  int iters = 0;
+  bool converged = false;
+  while (true) {
+    std::vector<double> Gk((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Gk[(size_t)i * k + j] = G[(size_t)i * kmax + j];
+    jacobi_eigh(k, Gk, ev, Y);
+    int imin = (int)(std::min_element(ev.begin(), ev.end()) - ev.begin());
+    theta = ev[imin];
+    std::vector<double> y(k);
+    for (int i = 0; i < k; ++i) y[i] = Y[(size_t)i * k + imin];
+    DMRG_HIP(hipMemcpyAsync(cc, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_lincomb(u, V, n, k, cc, n, 0.0, s);
+    launch_lincomb(w, W, n, k, cc, n, 0.0, s);
+    DMRG_HIP(hipMemcpyAsync(r, w, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_axpy(r, -theta, u, n, s);
+    rnorm = std::sqrt(std::max(0.0, dot(r, r)));
+    hist.push_back(rnorm);
+    res.residual_history.push_back(rnorm);
+    res.stage_history.push_back(stage);
+    const bool last = stage == nst - 1;
+    const double thr = last ? o.tol : o.ladder_tol[stage];
+    bool stalled = false;
+    if (!last && hist.size() >= 4) {
+      const double prev = hist[hist.size() - 4];
+      stalled = rnorm > 0.7 * prev;
+    }
+    if (rnorm < thr || stalled) {
+      if (last) { converged = rnorm < o.tol; break; }
+      // next ladder stage: restart from the Ritz vector with a fresh sigma
+      ++stage;
+      hist.clear();
+      const double un = std::sqrt(dot(u, u));
+      DMRG_HIP(hipMemcpyAsync(V, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      launch_scale(V, 1.0 / un, n, s);
+      sigma(V, W, prec_of(stage));
+      k = 1;
+      fill_col(0);
+      continue;
+    }
+    if (iters >= o.max_iter) break;
+    ++iters;
+    // correction t = r / (theta - diag), orthogonalised twice against V
+    launch_precondition(t, r, d, theta, n, s);
+    for (int pass = 0; pass < 2; ++pass) {
+      launch_multidot(h, V, n, k, t, n, s);
+      DMRG_HIP(hipMemcpyAsync(hh.data(), h, k * sizeof(double), hipMemcpyDeviceToHost, s));
+      DMRG_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i < k; ++i) hh[i] = -hh[i];
+      DMRG_HIP(hipMemcpyAsync(cc, hh.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+      launch_lincomb(t, V, n, k, cc, n, 1.0, s);
+    }
+    double tn = std::sqrt(dot(t, t));
+    if (k == kmax || !(tn > 1e-14)) {
+      // thick restart: keep the m lowest Ritz vectors (V Y_m, W Y_m)
+      const int m = std::min(k, std::max(1, std::min(o.restart, kmax - 1)));
+      std::vector<int> order(k);
+      for (int i = 0; i < k; ++i) order[i] = i;
+      std::sort(order.begin(), order.end(), [&](int a, int b) { return ev[a] < ev[b]; });
+      if (tmpV.bytes < (size_t)m * n * sizeof(double)) {
+        tmpV.alloc((size_t)m * n * sizeof(double));
+        tmpW.alloc((size_t)m * n * sizeof(double));
+      }
+      for (int j = 0; j < m; ++j) {
+        std::vector<double> yj(k);
+        for (int i = 0; i < k; ++i) yj[i] = Y[(size_t)i * k + order[j]];
+        DMRG_HIP(hipMemcpyAsync(cc, yj.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_lincomb(tmpV.as<double>() + (int64_t)j * n, V, n, k, cc, n, 0.0, s);
+        launch_lincomb(tmpW.as<double>() + (int64_t)j * n, W, n, k, cc, n, 0.0, s);
+        DMRG_HIP(hipStreamSynchronize(s));
+      }
+      DMRG_HIP(hipMemcpyAsync(V, tmpV.p, (size_t)m * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      DMRG_HIP(hipMemcpyAsync(W, tmpW.p, (size_t)m * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      k = m;
+      for (int j = 0; j < m; ++j) fill_col(j);
+      // re-orthogonalise t against the restarted basis
+      for (int pass = 0; pass < 2; ++pass) {
+        launch_multidot(h, V, n, k, t, n, s);
+        DMRG_HIP(hipMemcpyAsync(hh.data(), h, k * sizeof(double), hipMemcpyDeviceToHost, s));
+        DMRG_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < k; ++i) hh[i] = -hh[i];
+        DMRG_HIP(hipMemcpyAsync(cc, hh.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_lincomb(t, V, n, k, cc, n, 1.0, s);
+      }
+      tn = std::sqrt(dot(t, t));
+      if (!(tn > 1e-14)) continue;
+    }
+    DMRG_HIP(hipMemcpyAsync(V + (int64_t)k * n, t, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_scale(V + (int64_t)k * n, 1.0 / tn, n, s);
+    sigma(V + (int64_t)k * n, W + (int64_t)k * n, prec_of(stage));
+    fill_col(k);
+    ++k;
+  }
+  // final FP64 Rayleigh quotient of the normalised Ritz vector
+  const double un = std::sqrt(dot(u, u));
+  launch_scale(u, 1.0 / un, n, s);
+  sigma(u, w, 0);
+  res.energy = dot(u, w);
+  DMRG_HIP(hipMemcpyAsync(r, w, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_axpy(r, -res.energy, u, n, s);
+  res.residual = std::sqrt(std::max(0.0, dot(r, r)));
+  DMRG_HIP(hipMemcpyAsync(psi, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  DMRG_HIP(hipStreamSynchronize(s));
+  res.iterations = iters;
+  res.converged = converged || res.residual < o.tol;
+  res.time_ms = now_ms() - t_start;
+  return res.converged ? kOk : kWarnNotConverged;
+}
+
+}  // namespace dmrg

@@ -660,6 +660,12 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     add_pair(1, w.second, z, y, 1.0);
   }
   // ---- finalise pairs ------------------------------------------------------
+  const OpRef* hL = L.get({kHam, 0});
+  int zH = -1;
+  {
+    auto it = zindex.find(OpKey{kHam, 0});
+    if (it != zindex.end()) zH = it->second;
+  }
   for (auto& r : zrefs) {
     const OpClass& c = *R.classes[r.cls];
     plan->zops.push_back({c.op(r.idx), &c.L});
@@ -674,22 +680,52 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
       for (int b = 0; b < 16; ++b)
         if (kv.second.y.m[a][b] != 0) { nz = true; break; }
     if (!nz) continue;
-    plan->pairs.push_back({{c.op(k.lidx), &c.L}, k.z, kv.second.y, kv.second.ypar});
+    SigmaPair sp{{c.op(k.lidx), &c.L}, k.z, kv.second.y, kv.second.ypar};
+    sp.pinned = (k.lsrc == 0 && hL && k.lcls == hL->cls && k.lidx == hL->idx) ||
+                (k.z >= 0 && k.z == zH);
+    plan->pairs.push_back(sp);
   }
 
   // ---- execution schedule ----------------------------------------------------
   const PsiLayout& ps = plan->psi;
-  plan->psi_in.alloc((size_t)std::max<int64_t>(1, ps.size) * sizeof(double));
-  plan->sigma_out.alloc((size_t)std::max<int64_t>(1, ps.size) * sizeof(double));
-  const double* PSI = plan->psi_in.as<double>();
-  double* SIG = plan->sigma_out.as<double>();
+  // buffer registry: every operator class, then psi, sigma, workspace
+  std::map<const double*, int> buf_of_class;
+  auto reg_env = [&](const Env& e) {
+    for (auto& c : e.classes) {
+      PlanBuf b;
+      b.f64 = c->data.as<double>();
+      b.n = (int64_t)c->nops * c->L.nnz;
+      b.is_operator = true;
+      buf_of_class[b.f64] = (int)plan->bufs.size();
+      plan->bufs.push_back(std::move(b));
+    }
+  };
+  reg_env(L);
+  reg_env(W);
+  reg_env(R);
+  auto own = [&](int64_t n) {
+    PlanBuf b;
+    b.n = n;
+    b.own.alloc((size_t)std::max<int64_t>(1, n) * sizeof(double));
+    b.f64 = b.own.as<double>();
+    plan->bufs.push_back(std::move(b));
+    return (int)plan->bufs.size() - 1;
+  };
+  plan->buf_psi = own(ps.size);
+  plan->buf_sig = own(ps.size);
+  // locate an operator pointer inside its class buffer
+  auto ref_of = [&](const double* p) -> BufRef {
+    auto it = buf_of_class.upper_bound(p);
+    DMRG_REQUIRE(it != buf_of_class.begin(), kErrState, "plan_sigma: pointer outside operators");
+    --it;
+    return BufRef{it->second, (int64_t)(p - it->first)};
+  };
   // stage-1 sizes per z
   const int nz = (int)plan->zops.size();
   std::vector<int64_t> zsize(nz, 0);
   for (int z = 0; z < nz; ++z)
     for (auto& blk : plan->zops[z].lay->blk)
       if (ps.rows_of[blk.c] > 0 && ps.rows_of[blk.r] > 0) zsize[z] += ps.rows_of[blk.c] * br.d[blk.r];
-  // chunks of z
   std::vector<std::pair<int, int>> chunks;
   {
     int z0 = 0;
@@ -705,34 +741,36 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     }
     chunks.push_back({z0, nz});
   }
-  plan->ws.alloc((size_t)std::max<int64_t>(1, plan->ws_doubles) * sizeof(double));
-  double* WS = plan->ws.as<double>();
-  // pairs by z
+  plan->buf_ws = own(plan->ws_doubles);
+  const int BP = plan->buf_psi, BS = plan->buf_sig, BW = plan->buf_ws;
+  auto schedule = [&](bool pinned_set, const std::vector<std::pair<int, int>>& chunk_list,
+                      std::vector<AStage>& out1, std::vector<AStage>& out2) {
   std::map<int, std::vector<int>> pairs_of_z;
-  for (size_t k = 0; k < plan->pairs.size(); ++k) pairs_of_z[plan->pairs[k].z].push_back((int)k);
-  for (size_t ci = 0; ci < chunks.size(); ++ci) {
-    const int z0 = chunks[ci].first, z1 = chunks[ci].second;
-    GemmBatch b1;
-    // T_z(r) location: (z, r) -> pointer, width d_r'
-    std::map<std::pair<int, int>, std::pair<double*, int>> tloc;
+  for (size_t k = 0; k < plan->pairs.size(); ++k)
+    if (plan->pairs[k].pinned == pinned_set) pairs_of_z[plan->pairs[k].z].push_back((int)k);
+  std::set<int> zused;
+  for (auto& pz : pairs_of_z) zused.insert(pz.first);
+  for (size_t ci = 0; ci < chunk_list.size(); ++ci) {
+    const int z0 = chunk_list[ci].first, z1 = chunk_list[ci].second;
+    AStage st1, st2;
+    std::map<std::pair<int, int>, std::pair<int64_t, int>> tloc;  // (z, r) -> (ws offset, width)
     int64_t off = 0;
     for (int z = z0; z < z1; ++z) {
+      if (!zused.count(z)) continue;
       const OpView& Z = plan->zops[z];
-      const double sgn_par = plan->zpar[z];
       for (auto& blk : Z.lay->blk) {
         const int r = blk.c, rp = blk.r;
         if (ps.rows_of[r] == 0 || ps.rows_of[rp] == 0) continue;
-        double* T = WS + off;
+        tloc[{z, r}] = {off, br.d[rp]};
+        const double alpha = (plan->zpar[z] && (br.q[r].n & 1)) ? -1.0 : 1.0;
+        const int64_t s0 = (int64_t)st1.segs.size();
+        st1.segs.push_back({{BP, ps.off[r]}, ref_of(Z.data + blk.off), br.d[r], br.d[r], br.d[r], kTransB, alpha});
+        st1.probs.push_back({{BW, off}, br.d[rp], (int)ps.rows_of[r], br.d[rp], s0, s0 + 1, 0});
+        st1.flops += 2.0 * ps.rows_of[r] * br.d[rp] * br.d[r];
         off += ps.rows_of[r] * br.d[rp];
-        tloc[{z, r}] = {T, br.d[rp]};
-        const double alpha = (sgn_par && (br.q[r].n & 1)) ? -1.0 : 1.0;
-        const size_t s0 = b1.segs.size();
-        b1.segs.push_back({PSI + ps.off[r], Z.data + blk.off, br.d[r], br.d[r], br.d[r], kTransB, alpha});
-        b1.add_problem(T, br.d[rp], (int)ps.rows_of[r], br.d[rp], s0, s0 + 1, 0);
       }
     }
-    // stage 2: output rows (r', l', n') collect segments
-    std::map<std::tuple<int, int64_t>, std::vector<GemmSeg>> outs;
+    std::map<std::tuple<int, int64_t>, std::vector<ASeg>> outs;
     std::map<std::tuple<int, int64_t>, int> out_m;
     auto zin = [&](int z) { return z == -1 ? ci == 0 : (z >= z0 && z < z1); };
     for (auto& pz : pairs_of_z) {
@@ -740,6 +778,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
       for (int k : pz.second) {
         const SigmaPair& pr = plan->pairs[k];
         const Layout& Ll = *pr.L.lay;
+        const BufRef lref = ref_of(pr.L.data);
         for (int np = 0; np < 16; ++np)
           for (int n = 0; n < 16; ++n) {
             const double yv = pr.y.m[np][n];
@@ -754,59 +793,143 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
               auto kr = ps.row_of[r].find({l, n});
               auto krp = ps.row_of[rp].find({lp, np});
               if (kr == ps.row_of[r].end() || krp == ps.row_of[rp].end()) continue;
-              const double* Bp;
+              BufRef bref;
               int ldb;
               if (pr.z < 0) {
                 if (r != rp) continue;
-                Bp = PSI + ps.off[r] + kr->second * br.d[r];
+                bref = {BP, ps.off[r] + kr->second * br.d[r]};
                 ldb = br.d[r];
               } else {
                 auto it = tloc.find({pr.z, r});
                 if (it == tloc.end()) continue;
                 const Layout::Blk* zb = plan->zops[pr.z].lay->col(r);
                 if (!zb || zb->r != rp) continue;
-                Bp = it->second.first + kr->second * it->second.second;
+                bref = {BW, it->second.first + kr->second * it->second.second};
                 ldb = it->second.second;
               }
               const double sg = ((pr.ypar & 1) && (bl.q[l].n & 1)) ? -1.0 : 1.0;
               auto ok = std::make_tuple(rp, krp->second);
-              outs[ok].push_back({pr.L.data + lb.off, Bp, lb.dc, ldb, lb.dc, 0, yv * sg});
+              outs[ok].push_back({{lref.buf, lref.off + lb.off}, bref, lb.dc, ldb, lb.dc, 0, yv * sg});
               out_m[ok] = lb.dr;
             }
           }
       }
     }
-    GemmBatch b2;
     for (auto& o : outs) {
       const int rp = std::get<0>(o.first);
       const int64_t row = std::get<1>(o.first);
-      const size_t s0 = b2.segs.size();
-      for (auto& sgm : o.second) b2.segs.push_back(sgm);
-      b2.add_problem(SIG + ps.off[rp] + row * br.d[rp], br.d[rp], out_m[o.first], br.d[rp], s0,
-                     b2.segs.size(), 1);
+      const int64_t s0 = (int64_t)st2.segs.size();
+      const int mrows = out_m[o.first];
+      for (auto& sgm : o.second) {
+        st2.segs.push_back(sgm);
+        st2.flops += 2.0 * mrows * br.d[rp] * sgm.k;
+      }
+      st2.probs.push_back({{BS, ps.off[rp] + row * br.d[rp]}, br.d[rp], mrows, br.d[rp], s0,
+                           (int64_t)st2.segs.size(), 1});
     }
-    // largest tiles first (longest segment lists)
-    std::stable_sort(b2.tiles.begin(), b2.tiles.end(), [](const GemmTile& a, const GemmTile& b) {
-      return (a.seg_end - a.seg_begin) > (b.seg_end - b.seg_begin);
-    });
-    plan->flops += b1.flops + b2.flops;
-    plan->stage1.emplace_back();
-    upload_gemm(b1, plan->stage1.back());
-    plan->stage2.emplace_back();
-    upload_gemm(b2, plan->stage2.back());
+    plan->flops += st1.flops + st2.flops;
+    plan->flops_stage1 += st1.flops;
+    plan->flops_stage2 += st2.flops;
+    out1.push_back(std::move(st1));
+    out2.push_back(std::move(st2));
   }
+  };
+  schedule(false, chunks, plan->s1, plan->s2);
+  {
+    // the pinned pairs in one extra chunk (their stage-1 results fit: one z)
+    std::vector<AStage> a1, a2;
+    schedule(true, {{0, nz}}, a1, a2);
+    plan->p1 = std::move(a1[0]);
+    plan->p2 = std::move(a2[0]);
+  }
+  // FP64 descriptors
+  auto mat64 = [&](const AStage& A, DevGemm& out) {
+      GemmBatch b;
+      b.segs.reserve(A.segs.size());
+      for (auto& g : A.segs)
+        b.segs.push_back({plan->bufs[g.a.buf].f64 + g.a.off, plan->bufs[g.b.buf].f64 + g.b.off,
+                          g.lda, g.ldb, g.k, g.flags, g.alpha});
+      for (auto& pb : A.probs)
+        b.add_problem(plan->bufs[pb.c.buf].f64 + pb.c.off, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
+                      (size_t)pb.s1, pb.beta);
+      std::stable_sort(b.tiles.begin(), b.tiles.end(), [](const GemmTile& x, const GemmTile& y) {
+        return (x.seg_end - x.seg_begin) > (y.seg_end - y.seg_begin);
+      });
+      upload_gemm(b, out);
+  };
+  plan->f64_s1.resize(plan->s1.size());
+  plan->f64_s2.resize(plan->s2.size());
+  for (size_t c = 0; c < plan->s1.size(); ++c) {
+    mat64(plan->s1[c], plan->f64_s1[c]);
+    mat64(plan->s2[c], plan->f64_s2[c]);
+  }
+  mat64(plan->p1, plan->f64_p1);
+  mat64(plan->p2, plan->f64_p2);
   return plan;
 }
 
-void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, hipStream_t s) {
-  const int64_t n = plan.psi.size;
-  DMRG_HIP(hipMemcpyAsync(plan.psi_in.p, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_fill(plan.sigma_out.as<double>(), 0.0, n, s);
-  for (size_t c = 0; c < plan.stage1.size(); ++c) {
-    launch_gemm_f64(plan.stage1[c], s);
-    launch_gemm_f64(plan.stage2[c], s);
+// BF16 hi/lo copies of every operator, the psi and workspace buffers, and the
+// BF16 descriptors (built once per plan, on first use).
+void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
+  if (plan.bf_ready) return;
+  for (size_t k = 0; k < plan.bufs.size(); ++k) {
+    PlanBuf& b = plan.bufs[k];
+    if ((int)k == plan.buf_sig) continue;
+    b.bf.alloc((size_t)std::max<int64_t>(1, 2 * b.n) * sizeof(uint16_t));
+    if (b.is_operator) launch_split_bf16(b.bf.as<uint16_t>(), b.f64, b.n, s);
   }
-  DMRG_HIP(hipMemcpyAsync(sigma, plan.sigma_out.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  auto bfp = [&](const BufRef& r) { return plan.bufs[r.buf].bf.as<uint16_t>() + r.off; };
+  for (size_t c = 0; c < plan.s1.size(); ++c) {
+    for (int stage = 1; stage <= 2; ++stage) {
+      const AStage& A = stage == 1 ? plan.s1[c] : plan.s2[c];
+      GemmBatchB b;
+      b.segs.reserve(A.segs.size());
+      for (auto& g : A.segs)
+        b.segs.push_back({bfp(g.a), bfp(g.b), plan.bufs[g.a.buf].n, plan.bufs[g.b.buf].n, g.lda,
+                          g.ldb, g.k, g.flags, g.alpha});
+      for (auto& pb : A.probs) {
+        if (stage == 1)
+          b.add_problem(bfp(pb.c), plan.bufs[pb.c.buf].n, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
+                        (size_t)pb.s1, 0);
+        else
+          b.add_problem(plan.bufs[pb.c.buf].f64 + pb.c.off, 0, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
+                        (size_t)pb.s1, pb.beta);
+      }
+      std::stable_sort(b.tiles.begin(), b.tiles.end(), [](const GemmTileB& x, const GemmTileB& y) {
+        return (x.seg_end - x.seg_begin) > (y.seg_end - y.seg_begin);
+      });
+      (stage == 1 ? plan.bf_s1 : plan.bf_s2).emplace_back();
+      upload_gemm_bf16(b, (stage == 1 ? plan.bf_s1 : plan.bf_s2).back());
+    }
+  }
+  DMRG_HIP(hipStreamSynchronize(s));
+  plan.bf_ready = true;
+}
+
+void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision, hipStream_t s) {
+  const int64_t n = plan.psi.size;
+  PlanBuf& P = plan.bufs[plan.buf_psi];
+  PlanBuf& S = plan.bufs[plan.buf_sig];
+  DMRG_HIP(hipMemcpyAsync(P.f64, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_fill(S.f64, 0.0, n, s);
+  // pairs pinned to FP64 first (they reuse the stage-1 workspace)
+  launch_gemm_f64(plan.f64_p1, s, 1);
+  launch_gemm_f64(plan.f64_p2, s, 2);
+  if (precision == 0) {
+    for (size_t c = 0; c < plan.f64_s1.size(); ++c) {
+      launch_gemm_f64(plan.f64_s1[c], s, 1);
+      launch_gemm_f64(plan.f64_s2[c], s, 2);
+    }
+  } else {
+    prepare_bf16(plan, s);
+    launch_split_bf16(P.bf.as<uint16_t>(), P.f64, n, s);
+    const bool x3 = precision == 2;
+    for (size_t c = 0; c < plan.bf_s1.size(); ++c) {
+      launch_gemm_bf16(plan.bf_s1[c], x3, kOutBf16, 1, s);
+      launch_gemm_bf16(plan.bf_s2[c], x3, kOutF64, 2, s);
+    }
+  }
+  DMRG_HIP(hipMemcpyAsync(sigma, S.f64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
 
 }  // namespace dmrg

@@ -8,6 +8,7 @@
 
 #include "common.h"
 #include "gemm.h"
+#include "gemm_bf16.h"
 #include "strings.h"
 
 namespace dmrg {
@@ -223,6 +224,37 @@ struct SigmaPair {
   int z;     // index into SigmaPlan::zops, -1 = identity
   Mat16 y;   // site matrix, coefficient folded in
   int ypar;  // fermion parity of the site string
+  bool pinned = false;  // always FP64 (block Hamiltonians: energy-sized diagonals)
+};
+
+// The sigma schedule is kept precision-agnostic: operands are (buffer id,
+// element offset) and are turned into device descriptors per precision.
+struct BufRef {
+  int buf = -1;
+  int64_t off = 0;
+};
+struct ASeg {
+  BufRef a, b;
+  int32_t lda, ldb, k, flags;
+  double alpha;
+};
+struct AProb {
+  BufRef c;
+  int32_t ldc, m, n;
+  int64_t s0, s1;
+  int32_t beta;
+};
+struct AStage {
+  std::vector<ASeg> segs;
+  std::vector<AProb> probs;
+  double flops = 0;
+};
+struct PlanBuf {
+  double* f64 = nullptr;  // FP64 data (not owned unless in own)
+  int64_t n = 0;          // elements
+  DevBuf own;             // storage when the plan owns the buffer
+  DevBuf bf;              // BF16 copy: hi at [0, n), lo at [n, 2n) (uint16)
+  bool is_operator = false;
 };
 
 struct SigmaPlan {
@@ -232,10 +264,19 @@ struct SigmaPlan {
   std::vector<OpView> zops;    // distinct right operators
   std::vector<int> zpar;
   std::vector<SigmaPair> pairs;
-  DevBuf psi_in, sigma_out;    // internal copies so descriptors stay fixed
-  DevBuf ws;                   // stage-1 intermediates
-  std::vector<DevGemm> stage1, stage2;  // per chunk
+  std::vector<PlanBuf> bufs;
+  int buf_psi = -1, buf_sig = -1, buf_ws = -1;
+  std::vector<AStage> s1, s2;  // per chunk (pairs not pinned to FP64)
+  AStage p1, p2;               // pairs pinned to FP64 (one chunk)
+  // materialised descriptors
+  std::vector<DevGemm> f64_s1, f64_s2;
+  DevGemm f64_p1, f64_p2;
+  std::vector<DevGemmB> bf_s1, bf_s2;
+  bool bf_ready = false;
+  DevBuf diag;                 // diag(H_eff) for the Davidson preconditioner
+  bool diag_ready = false;
   double flops = 0;            // algorithmic FLOPs of one sigma
+  double flops_stage1 = 0, flops_stage2 = 0;
   int64_t ws_doubles = 0;
 };
 
@@ -244,6 +285,8 @@ struct SigmaPlan {
 std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env& L, const Env& R,
                                       int64_t ws_budget_doubles, hipStream_t s);
 // sigma = H_eff psi (device pointers, right-sector-major psi layout).
-void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, hipStream_t s);
+// precision: 0 FP64, 1 BF16, 2 split-BF16x3.
+void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision, hipStream_t s);
+void prepare_bf16(SigmaPlan& plan, hipStream_t s);
 
 }  // namespace dmrg

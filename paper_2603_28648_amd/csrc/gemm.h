@@ -82,7 +82,7 @@ struct DevGemm {
   double flops = 0;
 };
 void upload_gemm(const GemmBatch& b, DevGemm& d);
-void launch_gemm_f64(const DevGemm& d, hipStream_t stream);
+void launch_gemm_f64(const DevGemm& d, hipStream_t stream, int role = 0);
 
 // ---- elementwise / BLAS-1 helpers (FP64) ----------------------------------
 void launch_scale(double* x, double a, int64_t n, hipStream_t s);

@@ -1,0 +1,60 @@
+// BF16 / split-BF16 grouped GEMM (task model of gemm.h with BF16 operands).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "gemm.h"
+
+namespace dmrg {
+
+enum : int { kOutBf16 = 0, kOutF64 = 1 };
+
+struct GemmSegB {
+  const uint16_t* a;  // bf16 hi; the lo part (split mode) is at a + alo
+  const uint16_t* b;
+  int64_t alo, blo;
+  int32_t lda, ldb, k, flags;
+  double alpha;
+};
+
+struct GemmTileB {
+  void* c;        // FP64 (kOutF64) or bf16 hi (kOutBf16; lo at c + clo)
+  int64_t clo;
+  int32_t ldc, m, n, row0, col0, seg_begin, seg_end, beta;
+};
+
+struct GemmBatchB {
+  std::vector<GemmSegB> segs;
+  std::vector<GemmTileB> tiles;
+  void add_problem(void* c, int64_t clo, int ldc, int m, int n, size_t s0, size_t s1, int beta) {
+    if (m <= 0 || n <= 0 || s1 <= s0) return;
+    for (int r = 0; r < m; r += kTileM)
+      for (int q = 0; q < n; q += kTileN) {
+        GemmTileB t;
+        t.c = c;
+        t.clo = clo;
+        t.ldc = ldc;
+        t.m = std::min(kTileM, m - r);
+        t.n = std::min(kTileN, n - q);
+        t.row0 = r;
+        t.col0 = q;
+        t.seg_begin = (int32_t)s0;
+        t.seg_end = (int32_t)s1;
+        t.beta = beta;
+        tiles.push_back(t);
+      }
+  }
+};
+
+struct DevGemmB {
+  DevBuf buf;
+  GemmSegB* segs = nullptr;
+  GemmTileB* tiles = nullptr;
+  size_t ntiles = 0, nsegs = 0;
+};
+
+void upload_gemm_bf16(const GemmBatchB& b, DevGemmB& d);
+void launch_gemm_bf16(const DevGemmB& d, bool x3, int out, int role, hipStream_t s);
+void launch_split_bf16(uint16_t* out, const double* x, int64_t n, hipStream_t s);
+
+}  // namespace dmrg

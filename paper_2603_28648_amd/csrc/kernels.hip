@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "gemm.h"
+#include "davidson.h"
 
 namespace dmrg {
 
@@ -19,6 +20,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // (rows interleaved across the four 16-lane groups).
 constexpr int kTK = 16;
 
+// ROLE only names the kernel for profilers: 0 = operator construction,
+// 1 = sigma stage 1 (psi x right operator), 2 = sigma stage 2 (left operator x T).
+template <int ROLE>
 __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ tiles,
                                                    const GemmSeg* __restrict__ segs) {
   __shared__ double As[kTK][kTileM + 1];
@@ -116,7 +120,7 @@ void launch_gemm_f64(const GemmBatch& b, DevBuf& scratch, hipStream_t stream) {
   const size_t nt = b.tiles.size();
   for (size_t off = 0; off < nt; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(nt - off, (size_t)1 << 30);
-    hipLaunchKernelGGL(k_gemm_f64, dim3(cnt), dim3(256), 0, stream, dtiles + off, dsegs);
+    hipLaunchKernelGGL(k_gemm_f64<0>, dim3(cnt), dim3(256), 0, stream, dtiles + off, dsegs);
   }
   DMRG_HIP(hipGetLastError());
   // descriptors come from pageable host memory: make sure the copies are done
@@ -138,10 +142,15 @@ void upload_gemm(const GemmBatch& b, DevGemm& d) {
   d.flops = b.flops;
 }
 
-void launch_gemm_f64(const DevGemm& d, hipStream_t stream) {
+void launch_gemm_f64(const DevGemm& d, hipStream_t stream, int role) {
   for (size_t off = 0; off < d.ntiles; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(d.ntiles - off, (size_t)1 << 30);
-    hipLaunchKernelGGL(k_gemm_f64, dim3(cnt), dim3(256), 0, stream, d.tiles + off, d.segs);
+    if (role == 1)
+      hipLaunchKernelGGL(k_gemm_f64<1>, dim3(cnt), dim3(256), 0, stream, d.tiles + off, d.segs);
+    else if (role == 2)
+      hipLaunchKernelGGL(k_gemm_f64<2>, dim3(cnt), dim3(256), 0, stream, d.tiles + off, d.segs);
+    else
+      hipLaunchKernelGGL(k_gemm_f64<0>, dim3(cnt), dim3(256), 0, stream, d.tiles + off, d.segs);
   }
   DMRG_HIP(hipGetLastError());
 }
@@ -263,6 +272,63 @@ void launch_row_scatter_add(double* dst, const double* src, const int64_t* dst_o
   if (nrows <= 0 || n <= 0) return;
   unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 64));
   hipLaunchKernelGGL(k_row_scatter_add, dim3(gx, nrows), dim3(256), 0, s, dst, src, dst_off, n);
+  DMRG_HIP(hipGetLastError());
+}
+
+// ---- Davidson helpers --------------------------------------------------------
+__global__ void k_extract_diag(const DiagTask* tasks) {
+  const DiagTask t = tasks[blockIdx.x];
+  for (int i = threadIdx.x; i < t.d; i += blockDim.x) t.dst[i] = t.src[(int64_t)i * (t.d + 1)];
+}
+void launch_extract_diag(const DiagTask* tasks, int ntasks, hipStream_t s) {
+  for (int off = 0; off < ntasks; off += 1 << 30) {
+    const int cnt = std::min(ntasks - off, 1 << 30);
+    hipLaunchKernelGGL(k_extract_diag, dim3(cnt), dim3(64), 0, s, tasks + off);
+  }
+  DMRG_HIP(hipGetLastError());
+}
+
+// diag[row][col] = sum_p yd[p][n(row)] * Ld[p][aL(row)] * Zd[p][offR + col]
+__global__ __launch_bounds__(256) void k_heff_diag(double* out, int64_t rows, int dr,
+                                                   const int64_t* rowinfo, int64_t offR,
+                                                   int npairs, const double* yd,
+                                                   const double* Ld, int64_t DL,
+                                                   const double* Zd, int64_t DR) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= rows * dr) return;
+  const int64_t row = e / dr;
+  const int col = (int)(e % dr);
+  const int64_t aL = rowinfo[2 * row];
+  const int n = (int)rowinfo[2 * row + 1];
+  double acc = 0.0;
+  for (int p = 0; p < npairs; ++p)
+    acc += yd[p * 16 + n] * Ld[p * DL + aL] * Zd[p * DR + offR + col];
+  out[e] = acc;
+}
+void launch_heff_diag(double* out, int64_t rows, int dr, const int64_t* rowinfo, int64_t offR,
+                      int npairs, const double* yd, const double* Ld, int64_t DL,
+                      const double* Zd, int64_t DR, hipStream_t s) {
+  const int64_t n = rows * dr;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_heff_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, out, rows, dr,
+                     rowinfo, offR, npairs, yd, Ld, DL, Zd, DR);
+  DMRG_HIP(hipGetLastError());
+}
+
+// t = r / (theta - d), the denominator clamped to |.| >= 1e-8 keeping its sign
+__global__ void k_precondition(double* t, const double* r, const double* d, double theta,
+                               int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double den = theta - d[i];
+    if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+    t[i] = r[i] / den;
+  }
+}
+void launch_precondition(double* t, const double* r, const double* d, double theta, int64_t n,
+                         hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_precondition, dim3(grid_for(n)), dim3(256), 0, s, t, r, d, theta, n);
   DMRG_HIP(hipGetLastError());
 }
 

@@ -72,3 +72,22 @@ def test_sigma_repeat_is_bitwise_deterministic(ctx):
     x = np.random.default_rng(4).normal(size=n)
     a, b = lib_sigma_flat(ctx, x), lib_sigma_flat(ctx, x)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("K,N,tsz,D,i", [(8, 8, 0, 64, 3), (12, 12, 0, 256, 5), (10, 9, 1, 200, 2)])
+def test_mixed_sigma_error_vs_fp64(ctx, K, N, tsz, D, i):
+    """BF16 and split-BF16x3 sigma against the FP64 sigma of the same plan."""
+    print(f"mixed sigma K={K} D={D} window={i}", flush=True)
+    h, eri, m = case(K, N, tsz, D, i)
+    n = lib_load(ctx, h, eri, m)
+    x = np.random.default_rng(5).normal(size=n)
+    x /= np.linalg.norm(x)
+    s64 = lib_sigma_flat(ctx, x, "fp64")
+    s16 = lib_sigma_flat(ctx, x, "bf16")
+    s48 = lib_sigma_flat(ctx, x, "bf16x3")
+    e16 = np.linalg.norm(s16 - s64) / np.linalg.norm(s64)
+    e48 = np.linalg.norm(s48 - s64) / np.linalg.norm(s64)
+    print(f"  rel err bf16 {e16:.2e} bf16x3 {e48:.2e}", flush=True)
+    assert e16 < 2e-2
+    assert e48 < 1e-4
+    assert e48 < e16 / 20
