@@ -18,9 +18,18 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  Plain definitions:
   below; tests pin it against the raw four-operator sum.
 * FCI: lowest eigenvalue of H on the determinants with fixed (N, 2Sz).
 
+* Reduced density matrices (transition form, <bra| . |ket>):
+      gamma_pq   = sum_s <a+_{ps} a_{qs}>            = <E_pq>
+      Gamma_pqrs = sum_{s,t} <a+_{ps} a+_{rt} a_{st} a_{qs}> = <E_pq E_rs> - delta_qr <E_ps>
+  so that <bra|H|ket> = sum h_pq gamma_pq + 1/2 sum (pq|rs) Gamma_pqrs, i.e.
+  gamma and Gamma / 2 are the derivatives of <bra|H|ket> with respect to the
+  integral entries (each entry an independent input).
+
 Pins: tests/test_oracle_fock.py (closed forms: g=0 orbital sums, two-site
 Hubbard, K=1; [H,N]=[H,Sz]=0 on the full Fock space; the raw spin-orbital
-Hamiltonian on tiny spaces).
+Hamiltonian on tiny spaces); tests/test_oracle_rdm.py (single-determinant
+closed form, contraction against the raw Hamiltonian, finite differences of
+the raw Hamiltonian, trace and permutation identities).
 """
 from itertools import combinations
 
@@ -198,3 +207,23 @@ def fci(n_orb, n_elec, two_sz, h, eri, nroots=1, dense_limit=6000):
                       v0=rng.normal(size=space.dim), maxiter=5000)
     o = np.argsort(w)
     return w[o][:nroots], v[:, o][:, :nroots], space
+
+
+def rdm12(space, bra, ket):
+    """Transition 1- and 2-RDM of two vectors of `space` (definitions above).
+
+    Returns gamma (K, K) and Gamma (K, K, K, K) with
+    gamma[p, q] = <bra|E_pq|ket> and
+    Gamma[p, q, r, s] = <bra|E_pq E_rs|ket> - delta_qr <bra|E_ps|ket>.
+    """
+    K = space.K
+    bra = np.asarray(bra, dtype=np.float64).ravel()
+    ket = np.asarray(ket, dtype=np.float64).ravel()
+    # <bra|E_pq = (E_qp|bra>)^T since E_pq^T = E_qp
+    B = np.stack([space.epq(q, p) @ bra for p in range(K) for q in range(K)])
+    C = np.stack([space.epq(r, s) @ ket for r in range(K) for s in range(K)])
+    gamma = (B @ ket).reshape(K, K)
+    Gamma = (B @ C.T).reshape(K, K, K, K)
+    for q in range(K):
+        Gamma[:, q, q, :] -= gamma
+    return gamma, Gamma
