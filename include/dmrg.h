@@ -151,6 +151,8 @@ typedef struct {
   int32_t n_ladder;      /* 1..4 */
   int32_t ladder[4];     /* DMRG_FP64 / DMRG_BF16 / DMRG_BF16X3 per stage */
   double ladder_tol[4];  /* stage-end residuals (all stages but the last) */
+  int32_t precondition;  /* 2: Olsen-corrected diag(H_eff) (recommended), 1: plain diag(H_eff), 0: none */
+  int32_t restart;       /* Ritz vectors kept at a thick restart (default 6) */
 } dmrg_davidson_opts;
 
 typedef struct {
@@ -164,6 +166,49 @@ typedef struct {
 
 dmrg_status dmrg_davidson(dmrg_ctx ctx, double* psi_inout, const dmrg_davidson_opts* opts,
                           double* energy_out, dmrg_davidson_stats* stats_out);
+
+/* Reverse mode of the sigma with respect to the integrals.  For window
+ * vectors psi and sigma_bar (device, psi layout of the current window;
+ * sigma_bar NULL means psi) and the current MPS, f = <sigma_bar, H_eff psi>
+ * is linear in the integrals of the Hamiltonian (Model section: the ab initio
+ * Hamiltonian with one- and two-electron integrals); its gradient is written
+ * to dh (K*K) and deri (K^4), device pointers, same index order as the
+ * integrals, overwritten:
+ *   dh[p][q]         = sum_s <sigma_bar| a+_ps a_qs |psi>             (gamma_pq)
+ *   deri[p][q][r][s] = 1/2 sum_{s,t} <sigma_bar| a+_ps a+_rt a_st a_qs |psi>
+ * in the full-space states of the MPS with the window vectors in place.  With
+ * sigma_bar = psi normalised these are dE/dh = gamma and dE/d(pq|rs) =
+ * Gamma_pqrs / 2 at fixed MPS (every entry an independent input).  The
+ * operator adjoints are carried back along both blocks, so the call rebuilds
+ * both blocks once (FP64); it synchronises the stream before returning. */
+dmrg_status dmrg_sigma_backward(dmrg_ctx ctx, const double* psi, const double* sigma_bar,
+                                double* dh, double* deri);
+
+/* Truncates the optimised window psi (device, current window (i, i+1)) and
+ * moves the window (two-site DMRG step; the truncation error of the Method
+ * section).  The reduced density matrix of the half of the window left
+ * behind is diagonalised per middle-bond sector and the max_bond_dim
+ * largest eigenvalues over all sectors are kept (ties: lower sector, then
+ * later index; eigenvalues below cutoff * largest are dropped).
+ *   direction +1: site i becomes the new left-canonical tensor, the window
+ *                 moves to (i+1, i+2); needs i+1 <= K-2.
+ *   direction -1: site i+1 becomes the new right-canonical tensor, the
+ *                 window moves to (i-1, i); needs i >= 1.
+ * The guess for the new window (psi carried over, White's transformation) is
+ * kept in the context: read it with dmrg_get_psi after dmrg_build_ops for the
+ * new window.  trunc_err_out: discarded weight / total weight (may be NULL),
+ * kept_out: new bond dimension (may be NULL).  Invalidates the cached block
+ * operators that depend on the changed tensors. */
+dmrg_status dmrg_truncate(dmrg_ctx ctx, const double* psi, int32_t direction, int32_t max_bond_dim,
+                          double cutoff, double* trunc_err_out, int32_t* kept_out);
+
+/* Copies the current window's guess left by dmrg_truncate (device pointer of
+ * length dmrg_psi_size). */
+dmrg_status dmrg_get_psi(dmrg_ctx ctx, double* out);
+
+/* Diagnostic: copies diag(H_eff) of the current window (the Davidson
+ * preconditioner; psi layout, device pointer, length dmrg_psi_size). */
+dmrg_status dmrg_debug_diag(dmrg_ctx ctx, double* out);
 
 /* Diagnostic: C = alpha * op(A) op(B) + beta * C with the library's grouped
  * GEMM kernel of the given precision, for kernel-level numerics tests.

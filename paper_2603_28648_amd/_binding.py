@@ -56,7 +56,8 @@ class SigmaInfo(ctypes.Structure):
 class DavidsonOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("max_subspace", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("n_ladder", ctypes.c_int32),
-                ("ladder", ctypes.c_int32 * 4), ("ladder_tol", ctypes.c_double * 4)]
+                ("ladder", ctypes.c_int32 * 4), ("ladder_tol", ctypes.c_double * 4),
+                ("precondition", ctypes.c_int32), ("restart", ctypes.c_int32)]
 
 
 class DavidsonStats(ctypes.Structure):
@@ -79,6 +80,13 @@ EXPORTS = {
     "dmrg_sigma_get_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SigmaInfo)]),
     "dmrg_davidson": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(DavidsonOpts),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(DavidsonStats)]),
+    "dmrg_truncate": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "dmrg_get_psi": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dmrg_sigma_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+    "dmrg_debug_diag": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -151,9 +159,11 @@ class Context:
         prob = None
         keep = []
         if h is not None:
+            self._n_orb = int(np.asarray(h).shape[0])
             h = np.ascontiguousarray(h, dtype=np.float64)
             eri = np.ascontiguousarray(eri, dtype=np.float64)
             keep += [h, eri]
+            self._e_core = float(e_core)
             prob = Problem(h.shape[0], int(n_elec), int(two_sz), 0, float(e_core), _ptr(h), _ptr(eri))
         mps = None
         if mps_arrays is not None:
@@ -187,8 +197,22 @@ class Context:
         self._check(self.lib.dmrg_sigma(self.h, _dev_ptr(psi), _dev_ptr(out), p), self.h)
         return out
 
+    def sigma_backward(self, psi, sigma_bar=None, dh=None, deri=None):
+        """Gradient of <sigma_bar, H_eff psi> with respect to h (K x K) and
+        (pq|rs) (K^4): the transition 1-RDM and half the 2-RDM."""
+        import torch
+        K = self._n_orb
+        if dh is None:
+            dh = torch.empty((K, K), dtype=torch.float64, device=psi.device)
+        if deri is None:
+            deri = torch.empty((K, K, K, K), dtype=torch.float64, device=psi.device)
+        lam = ctypes.c_void_p(None) if sigma_bar is None else _dev_ptr(sigma_bar)
+        self._check(self.lib.dmrg_sigma_backward(self.h, _dev_ptr(psi), lam, _dev_ptr(dh), _dev_ptr(deri)),
+                    self.h)
+        return dh, deri
+
     def davidson(self, psi, tol=1e-6, max_iter=100, max_subspace=24,
-                 ladder=(("fp64", None),)):
+                 ladder=(("fp64", None),), precondition=2, restart=6):
         """Lowest eigenpair at the current window; psi (device) is updated in place.
 
         ladder: sequence of (precision, stage-end residual); the last stage
@@ -196,6 +220,8 @@ class Context:
         o = DavidsonOpts()
         o.max_iter, o.max_subspace, o.tol = int(max_iter), int(max_subspace), float(tol)
         o.n_ladder = len(ladder)
+        o.precondition = int(precondition)
+        o.restart = int(restart)
         for k, (p, t) in enumerate(ladder):
             o.ladder[k] = PRECISIONS[p] if isinstance(p, str) else int(p)
             o.ladder_tol[k] = float(t) if t is not None else 0.0
@@ -211,6 +237,56 @@ class Context:
                 "n_sigma": {"fp64": st.n_sigma[0], "bf16": st.n_sigma[1], "bf16x3": st.n_sigma[2]},
                 "residual_history": list(st.residual_history[:n]),
                 "stage_history": list(st.stage_history[:n])}
+
+    def truncate(self, psi, direction, max_bond_dim, cutoff=0.0):
+        """Truncate the window and move it; returns (truncation error, kept bond dimension)."""
+        e = ctypes.c_double()
+        k = ctypes.c_int32()
+        self._check(self.lib.dmrg_truncate(self.h, _dev_ptr(psi), int(direction), int(max_bond_dim),
+                                           float(cutoff), ctypes.byref(e), ctypes.byref(k)), self.h)
+        return e.value, k.value
+
+    def get_psi(self, out):
+        self._check(self.lib.dmrg_get_psi(self.h, _dev_ptr(out)), self.h)
+        return out
+
+    def sweep(self, psi, n_sweeps, max_bond_dim, tol=1e-6, ladder=(("fp64", None),), log=None):
+        """Two-site sweeps from the loaded window; returns per-half-sweep energies.
+
+        psi: device tensor of the current window; the context's window must be
+        0 (start of a left-to-right sweep).  Each half-sweep optimises every
+        window once and turns at the chain end."""
+        import torch
+        K = self._n_orb
+        energies, trunc = [], []
+        cur = psi
+        site, direction = 0, +1
+        for sweep in range(2 * n_sweeps):
+            e_half = None
+            eps_max = 0.0
+            while True:
+                r = self.davidson(cur, tol=tol, ladder=ladder)
+                e_half = r["energy"]
+                at_end = (direction > 0 and site == K - 2) or (direction < 0 and site == 0)
+                move = -direction if at_end else direction
+                eps, kept = self.truncate(cur, move, max_bond_dim)
+                eps_max = max(eps_max, eps)
+                site += move
+                self.build_ops(site, move)
+                cur = torch.empty(self.psi_size(), dtype=torch.float64, device=cur.device)
+                self.get_psi(cur)
+                if log:
+                    log(f"half-sweep {sweep} window {site - move} E={e_half:.12f} eps={eps:.2e} D={kept}")
+                if at_end:
+                    direction = move
+                    break
+            energies.append(e_half)
+            trunc.append(eps_max)
+        return energies, trunc, cur
+
+    def debug_diag(self, out):
+        self._check(self.lib.dmrg_debug_diag(self.h, _dev_ptr(out)), self.h)
+        return out
 
     def debug_gemm(self, a, b, c, trans_a=False, trans_b=False, alpha=1.0, beta=0,
                    precision="fp64"):
@@ -229,3 +305,43 @@ class Context:
         info = SigmaInfo()
         self._check(self.lib.dmrg_sigma_get_info(self.h, p, ctypes.byref(info)), self.h)
         return {k: getattr(info, k) for k, _ in SigmaInfo._fields_ if k != "pad"}
+
+
+class DMRGEnergy:
+    """E(h, eri, psi) = psi^T H_eff(h, eri) psi (+ e_core psi^T psi) as a
+    torch.autograd.Function of the integrals and the window vector.
+
+    ``DMRGEnergy.apply(h, eri, psi, ctx)``: ctx is a Context whose operators
+    were built from exactly these integrals for the window psi belongs to
+    (the MPS outside the window is held fixed).  The backward returns
+    (E_bar * gamma, E_bar * Gamma / 2, 2 E_bar * H_eff psi) from
+    dmrg_sigma_backward and the sigma.
+    """
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, h, eri, psi, ctx):
+        if cls._fn is None:
+            import torch
+
+            class _F(torch.autograd.Function):
+                @staticmethod
+                def forward(fctx, h, eri, psi, c):
+                    if tuple(h.shape) != (c._n_orb, c._n_orb):
+                        raise ValueError("h does not match the context's problem")
+                    sig = torch.empty_like(psi)
+                    c.sigma(psi.detach().contiguous(), sig)
+                    fctx.save_for_backward(psi, sig)
+                    fctx.c = c
+                    return torch.dot(psi, sig) + c._e_core * torch.dot(psi, psi)
+
+                @staticmethod
+                def backward(fctx, gE):
+                    psi, sig = fctx.saved_tensors
+                    dh, deri = fctx.c.sigma_backward(psi.detach().contiguous())
+                    gpsi = 2.0 * gE * (sig + fctx.c._e_core * psi)
+                    return gE * dh, gE * deri, gpsi, None
+
+            cls._fn = _F
+        return cls._fn.apply(h, eri, psi, ctx)

@@ -18,7 +18,8 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdmrg_mi355x.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["kernels.hip", "kernels_bf16.hip", "engine.cpp", "davidson.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "kernels_bf16.hip", "engine.cpp", "davidson.cpp", "truncate.cpp",
+           "backward.cpp", "capi.cpp"]
 ARCH = "gfx950"
 
 
@@ -56,7 +57,8 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(one, SOURCES))
     tmp = OUT + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

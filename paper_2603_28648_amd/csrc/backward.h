@@ -1,0 +1,21 @@
+// Reverse mode of the two-site sigma with respect to the integrals.
+#pragma once
+#include "engine.h"
+
+namespace dmrg {
+
+struct BackwardStats {
+  double ms_chain = 0;   // rebuilding both blocks with provenance
+  double ms_window = 0;  // window adjoints
+  double ms_adjoint = 0; // adjoint renormalisation and integral contractions
+  int64_t n_groups = 0;  // component groups visited
+};
+
+// For fixed window vectors psi and lam (API layout of the window) and the
+// fixed MPS, f(h, eri) = <lam, H_eff(h, eri) psi> is linear in the integrals.
+// Writes its gradient to grad (host, K*K entries for h followed by K^4 for
+// eri, same index order as the integrals; overwritten).
+BackwardStats sigma_backward(const Problem& P, const Mps& m, int window, const double* psi,
+                             const double* lam, double* grad, int64_t ws_budget, hipStream_t s);
+
+}  // namespace dmrg

@@ -7,8 +7,10 @@
 #include <string>
 
 #include "../../include/dmrg.h"
+#include "backward.h"
 #include "davidson.h"
 #include "engine.h"
+#include "truncate.h"
 
 using namespace dmrg;
 
@@ -24,7 +26,13 @@ struct dmrg_ctx_s {
   std::unique_ptr<SigmaPlan> plan;
   DevBuf desc;
   int64_t ws_budget = (int64_t)1 << 30;  // doubles of sigma intermediates (8 GiB)
+  DevBuf next_psi;                       // guess for the window left by dmrg_truncate
+  int64_t next_size = -1;
 };
+
+// Blocks kept while growing along the chain (for sweeps); larger ones are
+// rebuilt on demand.
+static const size_t kCacheBytes = (size_t)1 << 30;
 
 static thread_local std::string g_err;
 
@@ -191,7 +199,9 @@ dmrg_status dmrg_build_ops(dmrg_ctx c, const dmrg_problem* problem, const dmrg_m
       c->left.erase(b);
       for (; b < site; ++b) {
         const double t0 = now_s();
-        cur = grow_left(c->P, c->m, *cur, c->desc, s);
+        auto nxt = grow_left(c->P, c->m, *cur, c->desc, s);
+        if (cur->bytes() < kCacheBytes) c->left[b] = std::move(cur);
+        cur = std::move(nxt);
         if (verbose())
           fprintf(stderr, "[dmrg] left block -> bond %d: %.2f s, %.2f GB\n", b + 1, now_s() - t0,
                   cur->bytes() / 1e9), fflush(stderr);
@@ -205,18 +215,20 @@ dmrg_status dmrg_build_ops(dmrg_ctx c, const dmrg_problem* problem, const dmrg_m
       c->right.erase(b);
       for (; b > site + 2; --b) {
         const double t0 = now_s();
-        cur = grow_right(c->P, c->m, *cur, c->desc, s);
+        auto nxt = grow_right(c->P, c->m, *cur, c->desc, s);
+        if (cur->bytes() < kCacheBytes) c->right[b] = std::move(cur);
+        cur = std::move(nxt);
         if (verbose())
           fprintf(stderr, "[dmrg] right block -> bond %d: %.2f s, %.2f GB\n", b - 1, now_s() - t0,
                   cur->bytes() / 1e9), fflush(stderr);
       }
       c->right[site + 2] = std::move(cur);
     }
-    // keep only the blocks that bracket this window
+    // large blocks away from this window are not kept
     for (auto it = c->left.begin(); it != c->left.end();)
-      it = (it->first != site) ? c->left.erase(it) : std::next(it);
+      it = (it->first != site && it->second->bytes() >= kCacheBytes) ? c->left.erase(it) : std::next(it);
     for (auto it = c->right.begin(); it != c->right.end();)
-      it = (it->first != site + 2) ? c->right.erase(it) : std::next(it);
+      it = (it->first != site + 2 && it->second->bytes() >= kCacheBytes) ? c->right.erase(it) : std::next(it);
     const double t0 = now_s();
     c->plan = plan_sigma(c->P, c->m, *c->left[site], *c->right[site + 2], c->ws_budget, s);
     DMRG_HIP(hipStreamSynchronize(s));
@@ -247,6 +259,29 @@ dmrg_status dmrg_sigma(dmrg_ctx c, const double* psi, double* sigma, int32_t pre
   });
 }
 
+dmrg_status dmrg_sigma_backward(dmrg_ctx c, const double* psi, const double* sigma_bar, double* dh,
+                                double* deri) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->plan, kErrState, "sigma_backward: call dmrg_build_ops first");
+    DMRG_REQUIRE(psi && dh && deri, kErrInvalidArg, "sigma_backward: NULL buffer");
+    const int K = c->P.K;
+    const size_t n1 = (size_t)K * K, n2 = n1 * n1;
+    std::vector<double> g(n1 + n2);
+    const double t0 = now_s();
+    BackwardStats st = sigma_backward(c->P, c->m, c->window, psi, sigma_bar ? sigma_bar : psi, g.data(),
+                                      c->ws_budget, c->stream);
+    DMRG_HIP(hipMemcpyAsync(dh, g.data(), n1 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    DMRG_HIP(hipMemcpyAsync(deri, g.data() + n1, n2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    DMRG_HIP(hipStreamSynchronize(c->stream));
+    if (verbose())
+      fprintf(stderr, "[dmrg] backward window %d: rebuild %.1f ms, window %.1f ms, chains %.1f ms, %lld groups (%.1f ms)\n",
+              c->window, st.ms_chain, st.ms_window, st.ms_adjoint, (long long)st.n_groups,
+              1e3 * (now_s() - t0));
+    return kOk;
+  });
+}
+
 dmrg_status dmrg_davidson(dmrg_ctx c, double* psi, const dmrg_davidson_opts* opts,
                           double* energy_out, dmrg_davidson_stats* stats) {
   if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
@@ -258,6 +293,8 @@ dmrg_status dmrg_davidson(dmrg_ctx c, double* psi, const dmrg_davidson_opts* opt
     o.max_subspace = opts->max_subspace;
     o.tol = opts->tol;
     o.n_ladder = opts->n_ladder;
+    o.precondition = opts->precondition;
+    if (opts->restart > 0) o.restart = opts->restart;
     DMRG_REQUIRE(o.max_iter >= 0 && o.max_subspace >= 3 && o.max_subspace <= 64, kErrInvalidArg,
                  "davidson: need max_iter >= 0 and 3 <= max_subspace <= 64");
     DMRG_REQUIRE(o.tol > 0, kErrInvalidArg, "davidson: tol must be positive");
@@ -293,6 +330,61 @@ dmrg_status dmrg_davidson(dmrg_ctx c, double* psi, const dmrg_davidson_opts* opt
       }
     }
     return st;
+  });
+}
+
+dmrg_status dmrg_truncate(dmrg_ctx c, const double* psi, int32_t direction, int32_t max_d,
+                          double cutoff, double* trunc_err, int32_t* kept) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->plan && c->have_mps, kErrState, "truncate: call dmrg_build_ops first");
+    DMRG_REQUIRE(psi, kErrInvalidArg, "truncate: NULL psi");
+    DMRG_REQUIRE(direction == 1 || direction == -1, kErrInvalidArg, "truncate: direction must be +1 or -1");
+    DMRG_REQUIRE(max_d >= 1 && cutoff >= 0, kErrInvalidArg, "truncate: need max_bond_dim >= 1, cutoff >= 0");
+    const int i = c->window, K = c->P.K;
+    DMRG_REQUIRE(!(direction > 0 && i + 1 > K - 2) && !(direction < 0 && i == 0), kErrInvalidArg,
+                 "truncate: the window cannot move further in this direction");
+    c->plan.reset();
+    TruncResult r = truncate_and_move(c->m, i, psi, direction, max_d, cutoff, c->next_psi, c->desc, c->stream);
+    // blocks that contain a changed tensor
+    if (direction > 0) {
+      for (auto it = c->left.begin(); it != c->left.end();) it = it->first >= i + 1 ? c->left.erase(it) : std::next(it);
+      for (auto it = c->right.begin(); it != c->right.end();) it = it->first <= i + 2 ? c->right.erase(it) : std::next(it);
+    } else {
+      for (auto it = c->right.begin(); it != c->right.end();) it = it->first <= i + 1 ? c->right.erase(it) : std::next(it);
+      for (auto it = c->left.begin(); it != c->left.end();) it = it->first >= i ? c->left.erase(it) : std::next(it);
+    }
+    c->window = i + direction;
+    c->next_size = r.next_size;
+    if (trunc_err) *trunc_err = r.trunc_err;
+    if (kept) *kept = r.kept;
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_get_psi(dmrg_ctx c, double* out) {
+  if (!c || !out) return fail(c, kErrInvalidArg, "NULL argument");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->next_size >= 0, kErrState, "get_psi: no guess (call dmrg_truncate first)");
+    DMRG_REQUIRE(c->plan && c->plan->psi.size == c->next_size, kErrState,
+                 "get_psi: call dmrg_build_ops for the new window first");
+    DMRG_HIP(hipMemcpyAsync(out, c->next_psi.p, c->next_size * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_debug_diag(dmrg_ctx c, double* out) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->plan, kErrState, "debug_diag: call dmrg_build_ops first");
+    DMRG_REQUIRE(out, kErrInvalidArg, "debug_diag: NULL buffer");
+    SigmaPlan& p = *c->plan;
+    if (!p.diag_ready) {
+      build_diagonal(p, c->m.bonds[c->window], c->m.bonds[c->window + 2], c->stream);
+      p.diag_ready = true;
+    }
+    DMRG_HIP(hipMemcpyAsync(out, p.diag.p, p.psi.size * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return kOk;
   });
 }
 
@@ -340,13 +432,28 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const d
       launch_gemm_f64(bt, c->desc, c->stream);
       return kOk;
     }
-    // BF16 copies (hi then lo) of the operand storage
-    const int64_t na = (int64_t)(trans_a ? k : m) * lda, nb = (int64_t)(trans_b ? n : k) * ldb;
+    // padded NT copies: A as m x pad8(k) rows, B as n x pad8(k) rows, then BF16 hi/lo
+    const int kp = (k + 7) & ~7;
+    std::vector<double> ha((size_t)(trans_a ? k : m) * lda), hb((size_t)(trans_b ? n : k) * ldb);
+    DMRG_HIP(hipStreamSynchronize(c->stream));
+    DMRG_HIP(hipMemcpy(ha.data(), a, ha.size() * sizeof(double), hipMemcpyDeviceToHost));
+    DMRG_HIP(hipMemcpy(hb.data(), b, hb.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> pa((size_t)m * kp, 0.0), pb((size_t)n * kp, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int q = 0; q < k; ++q)
+        pa[(size_t)i * kp + q] = trans_a ? ha[(size_t)q * lda + i] : ha[(size_t)i * lda + q];
+    for (int j = 0; j < n; ++j)
+      for (int q = 0; q < k; ++q)
+        pb[(size_t)j * kp + q] = trans_b ? hb[(size_t)j * ldb + q] : hb[(size_t)q * ldb + j];
+    const int64_t na = (int64_t)pa.size(), nb = (int64_t)pb.size();
+    DevBuf da(na * sizeof(double)), db(nb * sizeof(double));
+    DMRG_HIP(hipMemcpy(da.p, pa.data(), na * sizeof(double), hipMemcpyHostToDevice));
+    DMRG_HIP(hipMemcpy(db.p, pb.data(), nb * sizeof(double), hipMemcpyHostToDevice));
     DevBuf abf((size_t)2 * na * sizeof(uint16_t)), bbf((size_t)2 * nb * sizeof(uint16_t));
-    launch_split_bf16(abf.as<uint16_t>(), a, na, c->stream);
-    launch_split_bf16(bbf.as<uint16_t>(), b, nb, c->stream);
+    launch_split_bf16(abf.as<uint16_t>(), da.as<double>(), na, c->stream);
+    launch_split_bf16(bbf.as<uint16_t>(), db.as<double>(), nb, c->stream);
     GemmBatchB bt;
-    bt.segs.push_back({abf.as<uint16_t>(), bbf.as<uint16_t>(), na, nb, lda, ldb, k, flags, alpha});
+    bt.segs.push_back({abf.as<uint16_t>(), bbf.as<uint16_t>(), na, nb, kp, kp, k, kTransB, alpha});
     bt.add_problem(cc, 0, ldc, m, n, 0, 1, beta);
     DevGemmB d;
     upload_gemm_bf16(bt, d);

@@ -48,10 +48,10 @@ void build_diagonal(SigmaPlan& plan, const Bond& bl, const Bond& br, hipStream_t
     const SigmaPair& p = plan.pairs[use[q]];
     for (int n = 0; n < 16; ++n) hy[(size_t)q * 16 + n] = p.y.m[n][n];
     for (auto& b : p.L.lay->blk)
-      if (b.r == b.c) tasks.push_back({p.L.data + b.off, Ld.as<double>() + (int64_t)q * DL + bl.off[b.c], b.dc, 0});
+      if (b.r == b.c) tasks.push_back({p.L.data + b.off, Ld.as<double>() + (int64_t)q * DL + bl.off[b.c], b.dc, b.ld});
     if (p.z >= 0) {
       for (auto& b : plan.zops[p.z].lay->blk)
-        if (b.r == b.c) tasks.push_back({plan.zops[p.z].data + b.off, Zd.as<double>() + (int64_t)q * DR + br.off[b.c], b.dc, 0});
+        if (b.r == b.c) tasks.push_back({plan.zops[p.z].data + b.off, Zd.as<double>() + (int64_t)q * DR + br.off[b.c], b.dc, b.ld});
     } else {
       launch_fill(Zd.as<double>() + (int64_t)q * DR, 1.0, DR, s);
     }
@@ -142,10 +142,19 @@ int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult
   res = DavidsonResult();
   DevBuf Vb((size_t)kmax * n * sizeof(double)), Wb((size_t)kmax * n * sizeof(double));
   DevBuf ub(n * sizeof(double)), wb(n * sizeof(double)), rb(n * sizeof(double)),
-      tb(n * sizeof(double)), hb(64 * sizeof(double)), cb(128 * sizeof(double));
+      tb(n * sizeof(double)), hb(64 * sizeof(double)), cb(128 * sizeof(double)),
+      auxb(n * sizeof(double));
+  double* aux = auxb.as<double>();
   double *V = Vb.as<double>(), *W = Wb.as<double>(), *u = ub.as<double>(), *w = wb.as<double>(),
          *r = rb.as<double>(), *t = tb.as<double>(), *h = hb.as<double>(), *cc = cb.as<double>();
   const double* d = plan.diag.as<double>();
+  double dmin = 0;
+  {
+    std::vector<double> dh((size_t)n);
+    DMRG_HIP(hipMemcpyAsync(dh.data(), d, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    dmin = n > 0 ? *std::min_element(dh.begin(), dh.end()) : 0.0;
+  }
   std::vector<double> G((size_t)kmax * kmax, 0.0), hh(64);
   DevBuf tmpV, tmpW;
   std::vector<double> ev, Y;
@@ -225,8 +234,25 @@ int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult
     }
     if (iters >= o.max_iter) break;
     ++iters;
-    // correction t = r / (theta - diag), orthogonalised twice against V
-    launch_precondition(t, r, d, theta, n, s);
+    // correction t = r / (theta - diag), orthogonalised twice against V.
+    // (theta - diag)^-1 is a useful preconditioner only once theta is below
+    // the whole diagonal: while theta lies inside its range some
+    // denominators pass through zero and the correction is dominated by
+    // the few components where diag ~ theta, so those steps take t = r.
+    const bool below = theta < dmin;
+    if (o.precondition == 2 && below) {
+      // Olsen: t = M^-1 (r - eps u), eps = u.M^-1 r / u.M^-1 u, M = theta - diag;
+      // removes the component of M^-1 r along the Ritz vector that makes the
+      // plain correction degenerate when diag(H_eff) is a good approximation
+      launch_precondition(t, r, d, theta, n, s);
+      launch_precondition(aux, u, d, theta, n, s);
+      const double num = dot(u, t), den = dot(u, aux);
+      if (std::abs(den) > 1e-300) launch_axpy(t, -num / den, aux, n, s);
+    } else if (o.precondition == 1 && below) {
+      launch_precondition(t, r, d, theta, n, s);
+    } else {
+      DMRG_HIP(hipMemcpyAsync(t, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     for (int pass = 0; pass < 2; ++pass) {
       launch_multidot(h, V, n, k, t, n, s);
       DMRG_HIP(hipMemcpyAsync(hh.data(), h, k * sizeof(double), hipMemcpyDeviceToHost, s));

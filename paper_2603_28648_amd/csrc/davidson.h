@@ -7,15 +7,16 @@
 namespace dmrg {
 
 struct DiagTask {
-  const double* src;  // top-left element of a square block (row stride = d)
+  const double* src;  // top-left element of a square block (row stride = ld)
   double* dst;        // d consecutive outputs
-  int32_t d, pad;
+  int32_t d, ld;
 };
 
 struct DavidsonOpts {
   int max_iter = 100;     // correction vectors added (sigma products excluding restarts)
   int max_subspace = 24;
   int restart = 6;        // Ritz vectors kept at a thick restart
+  int precondition = 2;   // 2: Olsen-corrected diag(H_eff), 1: plain diag, 0: none
   double tol = 1e-6;      // ||H u - theta u||_2 with ||u|| = 1, last ladder stage
   int n_ladder = 1;       // number of precision stages
   int ladder[4] = {0, 0, 0, 0};

@@ -46,7 +46,7 @@ static void set_identity(Env& e, hipStream_t s) {
   OpClass& c = *e.classes[r->cls];
   std::vector<double> h((size_t)c.L.nnz, 0.0);
   for (auto& b : c.L.blk)
-    for (int i = 0; i < b.dr; ++i) h[(size_t)b.off + (size_t)i * b.dc + i] = 1.0;
+    for (int i = 0; i < b.dr; ++i) h[(size_t)b.off + (size_t)i * b.ld + i] = 1.0;
   DMRG_HIP(hipStreamSynchronize(s));
   DMRG_HIP(hipMemcpy(c.op(r->idx), h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
 }
@@ -99,23 +99,20 @@ struct Target {
   OpRef ref;
 };
 
-using CompMap = std::map<std::tuple<int, int, int, int, uint64_t>, double>;
+using CompMap = std::map<CompKey, double>;
 // key: (target cls, target idx, source cls, source idx, site-string key)
 
-void add_comp(CompMap& cm, const OpRef& t, const OpRef* src, const Str& y, double c) {
-  if (!src || c == 0.0) return;
-  cm[std::make_tuple(t.cls, t.idx, src->cls, src->idx, y.key())] += c;
+thread_local CompProv* g_rec = nullptr;  // set while a backward rebuild records provenance
+
+void add_comp(CompMap& cm, const OpRef& t, const OpRef* src, const Str& y, double c,
+              int64_t entry = -1, double factor = 0.0) {
+  if (!src || (c == 0.0 && !(g_rec && entry >= 0))) return;
+  const CompKey k = std::make_tuple(t.cls, t.idx, src->cls, src->idx, y.key());
+  cm[k] += c;
+  if (g_rec && entry >= 0) g_rec->prov[k].push_back({entry, factor});
 }
 
-struct Projection {
-  const double* src;
-  const Layout* sl;
-  Mat4 y;
-  int ypar;
-  double* dst;
-  const Layout* dl;
-  double alpha;
-};
+}  // namespace
 
 // Emits the two-stage GEMMs of a list of projections, in chunks bounded by the
 // intermediate workspace, and runs them.
@@ -178,7 +175,7 @@ void run_projections(int side, const Mps& m, int site, const std::vector<Project
               double* u = U + uoff;
               uoff += (int64_t)dlp * dr;
               const size_t t0 = b1.segs.size();
-              b1.segs.push_back({pr.src + xb->off, S + oa, dl, dr, dl, 0, 1.0});
+              b1.segs.push_back({pr.src + xb->off, S + oa, xb->ld, dr, dl, 0, 1.0});
               b1.add_problem(u, dr, dlp, dr, t0, t0 + 1, 0);
               double sg = ((pr.ypar & 1) && (oldb.q[l].n & 1)) ? -1.0 : 1.0;
               b2.segs.push_back({S + oap, u, drp, dr, dlp, kTransA, pr.alpha * yv * sg});
@@ -196,14 +193,14 @@ void run_projections(int side, const Mps& m, int site, const std::vector<Project
               double* u = U + uoff;
               uoff += (int64_t)drp * dl;
               const size_t t0 = b1.segs.size();
-              b1.segs.push_back({pr.src + xb->off, S + ob, dr, dr, dr, kTransB, 1.0});
+              b1.segs.push_back({pr.src + xb->off, S + ob, xb->ld, dr, dr, kTransB, 1.0});
               b1.add_problem(u, dl, drp, dl, t0, t0 + 1, 0);
               double sg = (xpar && (kSiteN[n] & 1)) ? -1.0 : 1.0;
               b2.segs.push_back({S + obp, u, drp, dl, drp, 0, pr.alpha * yv * sg});
             }
           }
         const size_t s1 = b2.segs.size();
-        b2.add_problem(pr.dst + tb.off, tb.dc, tb.dr, tb.dc, s0, s1, 1);
+        b2.add_problem(pr.dst + tb.off, tb.ld, tb.dr, tb.dc, s0, s1, 1);
       }
     }
     launch_gemm_f64(b1, desc, s);
@@ -211,6 +208,8 @@ void run_projections(int side, const Mps& m, int site, const std::vector<Project
     p = q;
   }
 }
+
+namespace {
 
 // Executes all components: new = sum coef * Proj(old (x) y).
 void execute(const Env& old, Env& neu, const CompMap& cm, const Mps& m, int site,
@@ -322,7 +321,8 @@ std::vector<int> site_so(int b) { return {2 * b, 2 * b + 1}; }
 
 // ---------------------------------------------------------------------------
 std::unique_ptr<Env> grow_left(const Problem& P, const Mps& m, const Env& old, DevBuf& desc,
-                               hipStream_t s) {
+                               hipStream_t s, CompProv* rec) {
+  g_rec = rec;
   const int b = old.bond;
   DMRG_REQUIRE(old.side > 0 && b < m.K, kErrState, "grow_left: bad block");
   DMRG_REQUIRE(!m.site[b].off.empty(), kErrState, "grow_left: site tensor missing");
@@ -365,7 +365,7 @@ std::unique_ptr<Env> grow_left(const Problem& P, const Mps& m, const Env& old, D
         for (int k = 0; k < n; ++k) out += ix[k] > b;
         return out <= 1;
       },
-      [&](double c, const Str& term) {
+      [&](double c, const Str& term, int64_t ent, double fac) {
         Str parts[3];
         int sg = split_regions(term, region, 3, parts);
         if (sg == 0) return;
@@ -374,10 +374,10 @@ std::unique_ptr<Env> grow_left(const Problem& P, const Mps& m, const Env& old, D
         if (z.n == 0) t = tH;
         else if (z.n == 1 && x.n + y.n == 3) t = *e->get({kComp, z.key()});
         else return;
-        if (x.n == 0) add_comp(cm, t, oldI, y, c * sg);
+        if (x.n == 0) add_comp(cm, t, oldI, y, c * sg, ent, fac * sg);
         else if (x.n == 3) return;                       // inside T of the old block
         else if (y.n == 0 && z.n == 0) return;           // inside H of the old block
-        else add_comp(cm, t, old.get({kNormal, x.key()}), y, c * sg);
+        else add_comp(cm, t, old.get({kNormal, x.key()}), y, c * sg, ent, fac * sg);
       });
   // pass-through of the old complementary operators and H
   Str none;
@@ -392,18 +392,20 @@ std::unique_ptr<Env> grow_left(const Problem& P, const Mps& m, const Env& old, D
       add_comp(cm, *e->get({kComp, w.key()}), old.get({kComp, w.key()}), none, 1.0);
     }
   e->allocate(s);
-  (void)tI;
   // the identity is exact by construction, not projected
   CompMap cm2;
   for (auto& kv : cm)
     if (!(std::get<0>(kv.first) == tI.cls && std::get<1>(kv.first) == tI.idx)) cm2.insert(kv);
+  if (rec) rec->coef = cm2;
+  g_rec = nullptr;
   execute(old, *e, cm2, m, b, desc, s);
   set_identity(*e, s);
   return e;
 }
 
 std::unique_ptr<Env> grow_right(const Problem& P, const Mps& m, const Env& old, DevBuf& desc,
-                                hipStream_t s) {
+                                hipStream_t s, CompProv* rec) {
+  g_rec = rec;
   const int b = old.bond - 1;  // the new site
   DMRG_REQUIRE(old.side < 0 && b >= 0, kErrState, "grow_right: bad block");
   DMRG_REQUIRE(!m.site[b].off.empty(), kErrState, "grow_right: site tensor missing");
@@ -439,7 +441,7 @@ std::unique_ptr<Env> grow_right(const Problem& P, const Mps& m, const Env& old, 
         for (int k = 0; k < n; ++k) out += ix[k] < b;
         return out <= 2;
       },
-      [&](double c, const Str& term) {
+      [&](double c, const Str& term, int64_t ent, double fac) {
         Str parts[3];
         int sg = split_regions(term, region, 3, parts);
         if (sg == 0) return;
@@ -450,9 +452,9 @@ std::unique_ptr<Env> grow_right(const Problem& P, const Mps& m, const Env& old, 
         else if (z.n == 1 && (inside == 1 || inside == 3)) t = *e->get({kComp, z.key()});
         else if (z.n == 2 && inside == 2) t = *e->get({kComp, z.key()});
         else return;
-        if (x.n == 0) add_comp(cm, t, oldI, y, c * sg);
+        if (x.n == 0) add_comp(cm, t, oldI, y, c * sg, ent, fac * sg);
         else if (z.n + y.n <= 2) return;                 // inside H, S or Q of the old block
-        else add_comp(cm, t, old.get({kNormal, x.key()}), y, c * sg);
+        else add_comp(cm, t, old.get({kNormal, x.key()}), y, c * sg, ent, fac * sg);
       });
   Str none;
   add_comp(cm, tH, old.get({kHam, 0}), none, 1.0);
@@ -476,6 +478,8 @@ std::unique_ptr<Env> grow_right(const Problem& P, const Mps& m, const Env& old, 
   CompMap cm2;
   for (auto& kv : cm)
     if (!(std::get<0>(kv.first) == tI.cls && std::get<1>(kv.first) == tI.idx)) cm2.insert(kv);
+  if (rec) rec->coef = cm2;
+  g_rec = nullptr;
   execute(old, *e, cm2, m, b, desc, s);
   set_identity(*e, s);
   return e;
@@ -483,29 +487,43 @@ std::unique_ptr<Env> grow_right(const Problem& P, const Mps& m, const Env& old, 
 
 // ---------------------------------------------------------------------------
 void PsiLayout::build(const Bond& bl, const Bond& br) {
-  rows_of.assign(br.size(), 0);
-  off.assign(br.size(), 0);
-  row_of.assign(br.size(), {});
-  size = 0;
-  for (size_t r = 0; r < br.size(); ++r) {
+  const size_t nr = br.size();
+  rows_of.assign(nr, 0);
+  off.assign(nr, 0);
+  row_of.assign(nr, {});
+  rows_pad.assign(nr, 0);
+  off_pad.assign(nr, 0);
+  offT.assign(nr, 0);
+  ld.assign(nr, 0);
+  row_pad_of.assign(nr, {});
+  size = size_pad = sizeT = 0;
+  for (size_t r = 0; r < nr; ++r) {
     for (size_t l = 0; l < bl.size(); ++l)
       for (int n1 = 0; n1 < 4; ++n1)
         for (int n2 = 0; n2 < 4; ++n2)
           if (bl.q[l] + kSiteQN[n1] + kSiteQN[n2] == br.q[r]) {
             row_of[r][{(int)l, 4 * n1 + n2}] = rows_of[r];
+            row_pad_of[r][{(int)l, 4 * n1 + n2}] = rows_pad[r];
             rows_of[r] += bl.d[l];
+            rows_pad[r] += pad8(bl.d[l]);
           }
+    ld[r] = pad8(br.d[r]);
     off[r] = size;
     size += rows_of[r] * br.d[r];
+    off_pad[r] = size_pad;
+    size_pad += rows_pad[r] * ld[r];
+    offT[r] = sizeT;
+    sizeT += (int64_t)br.d[r] * rows_pad[r];
   }
 }
 
 std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env& L, const Env& R,
-                                      int64_t ws_budget, hipStream_t s) {
+                                      int64_t ws_budget, hipStream_t s, bool record) {
   const int i = L.bond;
   DMRG_REQUIRE(L.side > 0 && R.side < 0 && R.bond == i + 2, kErrState, "plan_sigma: blocks do not bracket a window");
   auto plan = std::make_unique<SigmaPlan>();
   plan->window = i;
+  plan->record = record;
   const Bond& bl = m.bonds[i];
   const Bond& br = m.bonds[i + 2];
   plan->psi.build(bl, br);
@@ -562,7 +580,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
   std::map<std::pair<uint64_t, uint64_t>, QN> psum_dq;
   for_each_term(
       P, [](const int*, int) { return true; },
-      [&](double c, const Str& term) {
+      [&](double c, const Str& term, int64_t ent, double fac) {
         Str parts[3];
         int sg = split_regions(term, region, 3, parts);
         if (sg == 0) return;
@@ -575,6 +593,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
         auto key = std::make_pair(y.key(), xr.key());
         psum[key][{src->cls, src->idx}] += c * sg;
         psum_dq[key] = -(y.qn() + xr.qn());
+        if (plan->record) plan->psum_prov[key][{src->cls, src->idx}].push_back({ent, fac * sg});
       });
   Str none;
   // stored pass-through pairs
@@ -623,6 +642,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     OpRef r = W.add({kPsum, wid++}, psum_dq[kv.first]);
     wlist.push_back({kv.first, r});
   }
+  plan->wkeys = wlist;
   W.allocate(s);
   {
     // per W class: Coef (nW x nops of the source class) * source class
@@ -639,6 +659,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
           scls = t.first.first;
         }
       if (scls < 0) continue;
+      plan->w_src_cls[kv.first] = scls;
       const OpClass& Sc = *L.classes[scls];
       DMRG_REQUIRE(Sc.L.nnz == Wc.L.nnz, kErrState, "plan_sigma: layout mismatch");
       std::vector<double> C((size_t)Wc.nops * Sc.nops, 0.0);
@@ -666,6 +687,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     auto it = zindex.find(OpKey{kHam, 0});
     if (it != zindex.end()) zH = it->second;
   }
+  plan->zrefs = zrefs;
   for (auto& r : zrefs) {
     const OpClass& c = *R.classes[r.cls];
     plan->zops.push_back({c.op(r.idx), &c.L});
@@ -683,12 +705,17 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     SigmaPair sp{{c.op(k.lidx), &c.L}, k.z, kv.second.y, kv.second.ypar};
     sp.pinned = (k.lsrc == 0 && hL && k.lcls == hL->cls && k.lidx == hL->idx) ||
                 (k.z >= 0 && k.z == zH);
+    sp.lsrc = k.lsrc;
+    sp.lref = OpRef{k.lcls, k.lidx};
     plan->pairs.push_back(sp);
   }
 
   // ---- execution schedule ----------------------------------------------------
+  // Every product is "NT": A row-major with k contiguous, B stored (n x k).
+  //   stage 1: T_{z,r}^T (d_r' x rows_pad_r) = Z(r', r) * Psi_r^T
+  //   stage 2: sigma_pad rows (l', n') of r' += L(l', l) * [T_{z,r}^T or Psi_r^T]
+  //            columns of the row group (l, n)
   const PsiLayout& ps = plan->psi;
-  // buffer registry: every operator class, then psi, sigma, workspace
   std::map<const double*, int> buf_of_class;
   auto reg_env = [&](const Env& e) {
     for (auto& c : e.classes) {
@@ -708,24 +735,55 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     b.n = n;
     b.own.alloc((size_t)std::max<int64_t>(1, n) * sizeof(double));
     b.f64 = b.own.as<double>();
+    launch_fill(b.f64, 0.0, n, s);
     plan->bufs.push_back(std::move(b));
     return (int)plan->bufs.size() - 1;
   };
-  plan->buf_psi = own(ps.size);
-  plan->buf_sig = own(ps.size);
-  // locate an operator pointer inside its class buffer
+  plan->buf_psi = own(ps.size_pad);
+  plan->buf_sig = own(ps.size_pad);
+  plan->buf_psit = own(ps.sizeT);
   auto ref_of = [&](const double* p) -> BufRef {
     auto it = buf_of_class.upper_bound(p);
     DMRG_REQUIRE(it != buf_of_class.begin(), kErrState, "plan_sigma: pointer outside operators");
     --it;
     return BufRef{it->second, (int64_t)(p - it->first)};
   };
+  // pack / unpack / transpose tasks (API layout <-> padded)
+  {
+    std::vector<CopyTask> pk, up, tr;
+    double* P = plan->bufs[plan->buf_psi].f64;
+    double* S = plan->bufs[plan->buf_sig].f64;
+    double* T = plan->bufs[plan->buf_psit].f64;
+    for (size_t r = 0; r < br.size(); ++r) {
+      for (auto& kv : ps.row_of[r]) {
+        const int l = kv.first.first;
+        const int64_t rp = ps.row_pad_of[r].at(kv.first);
+        // API addresses are filled in at run time (offsets from the API base)
+        pk.push_back({reinterpret_cast<const double*>((ps.off[r] + kv.second * br.d[r]) * sizeof(double)),
+                      P + ps.off_pad[r] + rp * ps.ld[r], bl.d[l], br.d[r], br.d[r], ps.ld[r]});
+        up.push_back({S + ps.off_pad[r] + rp * ps.ld[r],
+                      reinterpret_cast<double*>((ps.off[r] + kv.second * br.d[r]) * sizeof(double)),
+                      bl.d[l], br.d[r], ps.ld[r], br.d[r]});
+      }
+      if (ps.rows_pad[r] > 0)
+        tr.push_back({P + ps.off_pad[r], T + ps.offT[r], (int)ps.rows_pad[r], br.d[r], ps.ld[r],
+                      (int)ps.rows_pad[r]});
+    }
+    plan->n_pack = (int)pk.size();
+    plan->n_trans = (int)tr.size();
+    plan->pack_tasks.alloc(std::max<size_t>(1, pk.size()) * sizeof(CopyTask));
+    plan->unpack_tasks.alloc(std::max<size_t>(1, up.size()) * sizeof(CopyTask));
+    plan->trans_tasks.alloc(std::max<size_t>(1, tr.size()) * sizeof(CopyTask));
+    plan->pack_host = pk;
+    plan->unpack_host = up;
+    DMRG_HIP(hipMemcpy(plan->trans_tasks.p, tr.data(), tr.size() * sizeof(CopyTask), hipMemcpyHostToDevice));
+  }
   // stage-1 sizes per z
   const int nz = (int)plan->zops.size();
   std::vector<int64_t> zsize(nz, 0);
   for (int z = 0; z < nz; ++z)
     for (auto& blk : plan->zops[z].lay->blk)
-      if (ps.rows_of[blk.c] > 0 && ps.rows_of[blk.r] > 0) zsize[z] += ps.rows_of[blk.c] * br.d[blk.r];
+      if (ps.rows_of[blk.c] > 0 && ps.rows_of[blk.r] > 0) zsize[z] += ps.rows_pad[blk.c] * br.d[blk.r];
   std::vector<std::pair<int, int>> chunks;
   {
     int z0 = 0;
@@ -742,101 +800,98 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     chunks.push_back({z0, nz});
   }
   plan->buf_ws = own(plan->ws_doubles);
-  const int BP = plan->buf_psi, BS = plan->buf_sig, BW = plan->buf_ws;
+  const int BP = plan->buf_psi, BS = plan->buf_sig, BW = plan->buf_ws, BT = plan->buf_psit;
   auto schedule = [&](bool pinned_set, const std::vector<std::pair<int, int>>& chunk_list,
                       std::vector<AStage>& out1, std::vector<AStage>& out2) {
-  std::map<int, std::vector<int>> pairs_of_z;
-  for (size_t k = 0; k < plan->pairs.size(); ++k)
-    if (plan->pairs[k].pinned == pinned_set) pairs_of_z[plan->pairs[k].z].push_back((int)k);
-  std::set<int> zused;
-  for (auto& pz : pairs_of_z) zused.insert(pz.first);
-  for (size_t ci = 0; ci < chunk_list.size(); ++ci) {
-    const int z0 = chunk_list[ci].first, z1 = chunk_list[ci].second;
-    AStage st1, st2;
-    std::map<std::pair<int, int>, std::pair<int64_t, int>> tloc;  // (z, r) -> (ws offset, width)
-    int64_t off = 0;
-    for (int z = z0; z < z1; ++z) {
-      if (!zused.count(z)) continue;
-      const OpView& Z = plan->zops[z];
-      for (auto& blk : Z.lay->blk) {
-        const int r = blk.c, rp = blk.r;
-        if (ps.rows_of[r] == 0 || ps.rows_of[rp] == 0) continue;
-        tloc[{z, r}] = {off, br.d[rp]};
-        const double alpha = (plan->zpar[z] && (br.q[r].n & 1)) ? -1.0 : 1.0;
-        const int64_t s0 = (int64_t)st1.segs.size();
-        st1.segs.push_back({{BP, ps.off[r]}, ref_of(Z.data + blk.off), br.d[r], br.d[r], br.d[r], kTransB, alpha});
-        st1.probs.push_back({{BW, off}, br.d[rp], (int)ps.rows_of[r], br.d[rp], s0, s0 + 1, 0});
-        st1.flops += 2.0 * ps.rows_of[r] * br.d[rp] * br.d[r];
-        off += ps.rows_of[r] * br.d[rp];
+    std::map<int, std::vector<int>> pairs_of_z;
+    for (size_t k = 0; k < plan->pairs.size(); ++k)
+      if (plan->pairs[k].pinned == pinned_set) pairs_of_z[plan->pairs[k].z].push_back((int)k);
+    std::set<int> zused;
+    for (auto& pz : pairs_of_z) zused.insert(pz.first);
+    for (size_t ci = 0; ci < chunk_list.size(); ++ci) {
+      const int z0 = chunk_list[ci].first, z1 = chunk_list[ci].second;
+      AStage st1, st2;
+      std::map<std::pair<int, int>, int64_t> tloc;  // (z, r) -> ws offset of T^T (d_r' x rows_pad_r)
+      int64_t off = 0;
+      for (int z = z0; z < z1; ++z) {
+        if (!zused.count(z)) continue;
+        const OpView& Z = plan->zops[z];
+        for (auto& blk : Z.lay->blk) {
+          const int r = blk.c, rp = blk.r;
+          if (ps.rows_of[r] == 0 || ps.rows_of[rp] == 0) continue;
+          tloc[{z, r}] = off;
+          const double alpha = (plan->zpar[z] && (br.q[r].n & 1)) ? -1.0 : 1.0;
+          const int64_t s0 = (int64_t)st1.segs.size();
+          st1.segs.push_back({ref_of(Z.data + blk.off), {BP, ps.off_pad[r]}, blk.ld, ps.ld[r], br.d[r], kTransB, alpha});
+          st1.probs.push_back({{BW, off}, (int)ps.rows_pad[r], br.d[rp], (int)ps.rows_pad[r], s0, s0 + 1, 0});
+          st1.flops += 2.0 * ps.rows_of[r] * br.d[rp] * br.d[r];
+          off += ps.rows_pad[r] * br.d[rp];
+        }
       }
-    }
-    std::map<std::tuple<int, int64_t>, std::vector<ASeg>> outs;
-    std::map<std::tuple<int, int64_t>, int> out_m;
-    auto zin = [&](int z) { return z == -1 ? ci == 0 : (z >= z0 && z < z1); };
-    for (auto& pz : pairs_of_z) {
-      if (!zin(pz.first)) continue;
-      for (int k : pz.second) {
-        const SigmaPair& pr = plan->pairs[k];
-        const Layout& Ll = *pr.L.lay;
-        const BufRef lref = ref_of(pr.L.data);
-        for (int np = 0; np < 16; ++np)
-          for (int n = 0; n < 16; ++n) {
-            const double yv = pr.y.m[np][n];
-            if (yv == 0) continue;
-            const QN qn = kSiteQN[n >> 2] + kSiteQN[n & 3];
-            const QN qnp = kSiteQN[np >> 2] + kSiteQN[np & 3];
-            for (auto& lb : Ll.blk) {
-              const int l = lb.c, lp = lb.r;
-              const int r = br.find(bl.q[l] + qn);
-              const int rp = br.find(bl.q[lp] + qnp);
-              if (r < 0 || rp < 0) continue;
-              auto kr = ps.row_of[r].find({l, n});
-              auto krp = ps.row_of[rp].find({lp, np});
-              if (kr == ps.row_of[r].end() || krp == ps.row_of[rp].end()) continue;
-              BufRef bref;
-              int ldb;
-              if (pr.z < 0) {
-                if (r != rp) continue;
-                bref = {BP, ps.off[r] + kr->second * br.d[r]};
-                ldb = br.d[r];
-              } else {
-                auto it = tloc.find({pr.z, r});
-                if (it == tloc.end()) continue;
-                const Layout::Blk* zb = plan->zops[pr.z].lay->col(r);
-                if (!zb || zb->r != rp) continue;
-                bref = {BW, it->second.first + kr->second * it->second.second};
-                ldb = it->second.second;
+      std::map<std::tuple<int, int64_t>, std::vector<ASeg>> outs;
+      std::map<std::tuple<int, int64_t>, int> out_m;
+      auto zin = [&](int z) { return z == -1 ? ci == 0 : (z >= z0 && z < z1); };
+      for (auto& pz : pairs_of_z) {
+        if (!zin(pz.first)) continue;
+        for (int k : pz.second) {
+          const SigmaPair& pr = plan->pairs[k];
+          const Layout& Ll = *pr.L.lay;
+          const BufRef lref = ref_of(pr.L.data);
+          for (int np = 0; np < 16; ++np)
+            for (int n = 0; n < 16; ++n) {
+              const double yv = pr.y.m[np][n];
+              if (yv == 0) continue;
+              const QN qn = kSiteQN[n >> 2] + kSiteQN[n & 3];
+              const QN qnp = kSiteQN[np >> 2] + kSiteQN[np & 3];
+              for (auto& lb : Ll.blk) {
+                const int l = lb.c, lp = lb.r;
+                const int r = br.find(bl.q[l] + qn);
+                const int rp = br.find(bl.q[lp] + qnp);
+                if (r < 0 || rp < 0) continue;
+                auto kr = ps.row_pad_of[r].find({l, n});
+                auto krp = ps.row_pad_of[rp].find({lp, np});
+                if (kr == ps.row_pad_of[r].end() || krp == ps.row_pad_of[rp].end()) continue;
+                BufRef bref;
+                if (pr.z < 0) {
+                  if (r != rp) continue;
+                  bref = {BT, ps.offT[r] + kr->second};
+                } else {
+                  auto it = tloc.find({pr.z, r});
+                  if (it == tloc.end()) continue;
+                  const Layout::Blk* zb = plan->zops[pr.z].lay->col(r);
+                  if (!zb || zb->r != rp) continue;
+                  bref = {BW, it->second + kr->second};
+                }
+                const double sg = ((pr.ypar & 1) && (bl.q[l].n & 1)) ? -1.0 : 1.0;
+                auto ok = std::make_tuple(rp, krp->second);
+                outs[ok].push_back({{lref.buf, lref.off + lb.off}, bref, lb.ld, (int)ps.rows_pad[r], lb.dc,
+                                    kTransB, yv * sg});
+                out_m[ok] = lb.dr;
               }
-              const double sg = ((pr.ypar & 1) && (bl.q[l].n & 1)) ? -1.0 : 1.0;
-              auto ok = std::make_tuple(rp, krp->second);
-              outs[ok].push_back({{lref.buf, lref.off + lb.off}, bref, lb.dc, ldb, lb.dc, 0, yv * sg});
-              out_m[ok] = lb.dr;
             }
-          }
+        }
       }
-    }
-    for (auto& o : outs) {
-      const int rp = std::get<0>(o.first);
-      const int64_t row = std::get<1>(o.first);
-      const int64_t s0 = (int64_t)st2.segs.size();
-      const int mrows = out_m[o.first];
-      for (auto& sgm : o.second) {
-        st2.segs.push_back(sgm);
-        st2.flops += 2.0 * mrows * br.d[rp] * sgm.k;
+      for (auto& o : outs) {
+        const int rp = std::get<0>(o.first);
+        const int64_t row = std::get<1>(o.first);
+        const int64_t s0 = (int64_t)st2.segs.size();
+        const int mrows = out_m[o.first];
+        for (auto& sgm : o.second) {
+          st2.segs.push_back(sgm);
+          st2.flops += 2.0 * mrows * br.d[rp] * sgm.k;
+        }
+        st2.probs.push_back({{BS, ps.off_pad[rp] + row * ps.ld[rp]}, ps.ld[rp], mrows, br.d[rp], s0,
+                             (int64_t)st2.segs.size(), 1});
       }
-      st2.probs.push_back({{BS, ps.off[rp] + row * br.d[rp]}, br.d[rp], mrows, br.d[rp], s0,
-                           (int64_t)st2.segs.size(), 1});
+      plan->flops += st1.flops + st2.flops;
+      plan->flops_stage1 += st1.flops;
+      plan->flops_stage2 += st2.flops;
+      out1.push_back(std::move(st1));
+      out2.push_back(std::move(st2));
     }
-    plan->flops += st1.flops + st2.flops;
-    plan->flops_stage1 += st1.flops;
-    plan->flops_stage2 += st2.flops;
-    out1.push_back(std::move(st1));
-    out2.push_back(std::move(st2));
-  }
   };
   schedule(false, chunks, plan->s1, plan->s2);
   {
-    // the pinned pairs in one extra chunk (their stage-1 results fit: one z)
     std::vector<AStage> a1, a2;
     schedule(true, {{0, nz}}, a1, a2);
     plan->p1 = std::move(a1[0]);
@@ -844,18 +899,18 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
   }
   // FP64 descriptors
   auto mat64 = [&](const AStage& A, DevGemm& out) {
-      GemmBatch b;
-      b.segs.reserve(A.segs.size());
-      for (auto& g : A.segs)
-        b.segs.push_back({plan->bufs[g.a.buf].f64 + g.a.off, plan->bufs[g.b.buf].f64 + g.b.off,
-                          g.lda, g.ldb, g.k, g.flags, g.alpha});
-      for (auto& pb : A.probs)
-        b.add_problem(plan->bufs[pb.c.buf].f64 + pb.c.off, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
-                      (size_t)pb.s1, pb.beta);
-      std::stable_sort(b.tiles.begin(), b.tiles.end(), [](const GemmTile& x, const GemmTile& y) {
-        return (x.seg_end - x.seg_begin) > (y.seg_end - y.seg_begin);
-      });
-      upload_gemm(b, out);
+    GemmBatch b;
+    b.segs.reserve(A.segs.size());
+    for (auto& g : A.segs)
+      b.segs.push_back({plan->bufs[g.a.buf].f64 + g.a.off, plan->bufs[g.b.buf].f64 + g.b.off,
+                        g.lda, g.ldb, g.k, g.flags, g.alpha});
+    for (auto& pb : A.probs)
+      b.add_problem(plan->bufs[pb.c.buf].f64 + pb.c.off, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
+                    (size_t)pb.s1, pb.beta);
+    std::stable_sort(b.tiles.begin(), b.tiles.end(), [](const GemmTile& x, const GemmTile& y) {
+      return (x.seg_end - x.seg_begin) > (y.seg_end - y.seg_begin);
+    });
+    upload_gemm(b, out);
   };
   plan->f64_s1.resize(plan->s1.size());
   plan->f64_s2.resize(plan->s2.size());
@@ -865,6 +920,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
   }
   mat64(plan->p1, plan->f64_p1);
   mat64(plan->p2, plan->f64_p2);
+  DMRG_HIP(hipStreamSynchronize(s));
   return plan;
 }
 
@@ -884,9 +940,13 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
       const AStage& A = stage == 1 ? plan.s1[c] : plan.s2[c];
       GemmBatchB b;
       b.segs.reserve(A.segs.size());
-      for (auto& g : A.segs)
+      for (auto& g : A.segs) {
+        DMRG_REQUIRE(g.flags == kTransB && g.lda % 8 == 0 && g.ldb % 8 == 0 && g.a.off % 8 == 0 &&
+                         g.b.off % 8 == 0,
+                     kErrState, "prepare_bf16: segment is not an aligned NT product");
         b.segs.push_back({bfp(g.a), bfp(g.b), plan.bufs[g.a.buf].n, plan.bufs[g.b.buf].n, g.lda,
                           g.ldb, g.k, g.flags, g.alpha});
+      }
       for (auto& pb : A.probs) {
         if (stage == 1)
           b.add_problem(bfp(pb.c), plan.bufs[pb.c.buf].n, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
@@ -906,12 +966,37 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
   plan.bf_ready = true;
 }
 
+// The pack/unpack task lists hold API offsets; the run binds them to the
+// caller's psi / sigma pointers (the lists are rebuilt only when the pointers
+// change, so repeated calls on the same buffers do no host work).
+static void bind_tasks(const std::vector<CopyTask>& host, DevBuf& dev, const double* api_src,
+                       double* api_dst, bool src_is_api, const double*& bound) {
+  const double* key = src_is_api ? api_src : api_dst;
+  if (bound == key) return;
+  std::vector<CopyTask> t = host;
+  for (auto& x : t) {
+    if (src_is_api) x.src = reinterpret_cast<const double*>(reinterpret_cast<const char*>(api_src) + reinterpret_cast<size_t>(x.src));
+    else x.dst = reinterpret_cast<double*>(reinterpret_cast<char*>(api_dst) + reinterpret_cast<size_t>(x.dst));
+  }
+  DMRG_HIP(hipMemcpy(dev.p, t.data(), t.size() * sizeof(CopyTask), hipMemcpyHostToDevice));
+  bound = key;
+}
+
+void plan_load_psi(SigmaPlan& plan, const double* psi, hipStream_t s) {
+  if (plan.bound_psi != psi) DMRG_HIP(hipStreamSynchronize(s));
+  bind_tasks(plan.pack_host, plan.pack_tasks, psi, nullptr, true, plan.bound_psi);
+  launch_copy_tasks(plan.pack_tasks.as<CopyTask>(), plan.n_pack, false, s);
+  launch_copy_tasks(plan.trans_tasks.as<CopyTask>(), plan.n_trans, true, s);
+}
+
 void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision, hipStream_t s) {
-  const int64_t n = plan.psi.size;
   PlanBuf& P = plan.bufs[plan.buf_psi];
   PlanBuf& S = plan.bufs[plan.buf_sig];
-  DMRG_HIP(hipMemcpyAsync(P.f64, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_fill(S.f64, 0.0, n, s);
+  PlanBuf& T = plan.bufs[plan.buf_psit];
+  if (plan.bound_sigma != sigma) DMRG_HIP(hipStreamSynchronize(s));
+  bind_tasks(plan.unpack_host, plan.unpack_tasks, nullptr, sigma, false, plan.bound_sigma);
+  plan_load_psi(plan, psi, s);
+  launch_fill(S.f64, 0.0, S.n, s);
   // pairs pinned to FP64 first (they reuse the stage-1 workspace)
   launch_gemm_f64(plan.f64_p1, s, 1);
   launch_gemm_f64(plan.f64_p2, s, 2);
@@ -922,14 +1007,15 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
     }
   } else {
     prepare_bf16(plan, s);
-    launch_split_bf16(P.bf.as<uint16_t>(), P.f64, n, s);
+    launch_split_bf16(P.bf.as<uint16_t>(), P.f64, P.n, s);
+    launch_split_bf16(T.bf.as<uint16_t>(), T.f64, T.n, s);
     const bool x3 = precision == 2;
     for (size_t c = 0; c < plan.bf_s1.size(); ++c) {
       launch_gemm_bf16(plan.bf_s1[c], x3, kOutBf16, 1, s);
       launch_gemm_bf16(plan.bf_s2[c], x3, kOutF64, 2, s);
     }
   }
-  DMRG_HIP(hipMemcpyAsync(sigma, S.f64, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_copy_tasks(plan.unpack_tasks.as<CopyTask>(), plan.n_pack, false, s);
 }
 
 }  // namespace dmrg

@@ -16,6 +16,7 @@ namespace dmrg {
 // ---- problem (integrals) ----------------------------------------------------
 struct Problem {
   int K = 0, N = 0, tsz = 0;
+  bool all_terms = false;  // enumerate terms with zero integrals too (backward)
   double e_core = 0;
   std::vector<double> h, eri;  // K*K and K^4, chemists' (pq|rs)
   double t(int P, int Q) const {
@@ -23,24 +24,26 @@ struct Problem {
   }
 };
 
-// Calls f(coef, str) for every nonzero term of
+// Calls f(coef, str, entry, factor) for every nonzero term of
 //   H = sum t_PQ a+_P a_Q + 1/2 sum V_PQRS a+_P a+_Q a_R a_S,
 //   V_PQRS = (ps|qr) d(s_P,s_S) d(s_Q,s_R)
 // restricted to spatial-index tuples accepted by keep(list, count).
+// coef = factor * (integral entry): entry indexes [h (K*K) | eri (K^4)].
 template <class Keep, class F>
 void for_each_term(const Problem& P, Keep&& keep, F&& f) {
   const int K = P.K;
+  const int64_t K2 = (int64_t)K * K;
   for (int p = 0; p < K; ++p)
     for (int q = 0; q < K; ++q) {
       const int ix[2] = {p, q};
       if (!keep(ix, 2)) continue;
       const double t = P.h[(size_t)p * K + q];
-      if (t == 0.0) continue;
+      if (t == 0.0 && !P.all_terms) continue;
       for (int a = 0; a < 2; ++a) {
         Str s;
         s.push(2 * p + a, 1);
         s.push(2 * q + a, 0);
-        f(t, s);
+        f(t, s, (int64_t)p * K + q, 1.0);
       }
     }
   for (int p = 0; p < K; ++p)
@@ -49,8 +52,9 @@ void for_each_term(const Problem& P, Keep&& keep, F&& f) {
         for (int u = 0; u < K; ++u) {
           const int ix[4] = {p, q, r, u};
           if (!keep(ix, 4)) continue;
-          const double g = P.eri[(((size_t)p * K + u) * K + q) * K + r];  // (pu|qr)
-          if (g == 0.0) continue;
+          const int64_t e = (((int64_t)p * K + u) * K + q) * K + r;  // (pu|qr)
+          const double g = P.eri[(size_t)e];
+          if (g == 0.0 && !P.all_terms) continue;
           for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) {
               const int A = 2 * p + a, B = 2 * q + b, C = 2 * r + b, D = 2 * u + a;
@@ -60,7 +64,7 @@ void for_each_term(const Problem& P, Keep&& keep, F&& f) {
               s.push(B, 1);
               s.push(C, 0);
               s.push(D, 0);
-              f(0.5 * g, s);
+              f(0.5 * g, s, K2 + e, 0.5);
             }
         }
 }
@@ -92,12 +96,17 @@ struct Bond {
 // Blocks of an operator with own quantum-number change dq acting on the
 // states of one bond.  Bond labels are the quantum numbers of the part left
 // of the bond, so for a left block row = col + dq and for a right block
-// row = col - dq.
+// row = col - dq.  Block rows are padded to a multiple of 8 elements (the
+// padding stays zero) so that every block row starts 16-byte aligned in the
+// BF16 copies and vector loads along a row never leave the block.
+inline int pad8(int x) { return (x + 7) & ~7; }
+inline int64_t pad8(int64_t x) { return (x + 7) & ~(int64_t)7; }
+
 struct Layout {
   QN dq;
   int side = +1;
   struct Blk {
-    int r, c, dr, dc;
+    int r, c, dr, dc, ld;
     int64_t off;
   };
   std::vector<Blk> blk;
@@ -114,8 +123,9 @@ struct Layout {
       int r = b.find(rq);
       if (r < 0) continue;
       by_col[c] = (int)blk.size();
-      blk.push_back({r, (int)c, b.d[r], b.d[c], nnz});
-      nnz += (int64_t)b.d[r] * b.d[c];
+      const int ld = pad8(b.d[c]);
+      blk.push_back({r, (int)c, b.d[r], b.d[c], ld, nnz});
+      nnz += (int64_t)b.d[r] * ld;
     }
   }
   const Blk* col(int c) const { return (c >= 0 && by_col[c] >= 0) ? &blk[by_col[c]] : nullptr; }
@@ -193,25 +203,67 @@ struct Mps {
   std::vector<SiteTensor> site;  // K (window sites may be empty)
 };
 
+// A projection dst += alpha * Proj(src (x) y) onto the next bond; side +1
+// projects a left-block operator with A_site, side -1 a right-block one with
+// B_site (dst and src are operators of the layouts dl / sl).
+struct Projection {
+  const double* src;
+  const Layout* sl;
+  Mat4 y;
+  int ypar;
+  double* dst;
+  const Layout* dl;
+  double alpha;
+};
+void run_projections(int side, const Mps& m, int site, const std::vector<Projection>& projs,
+                     DevBuf& desc, DevBuf& uws, int64_t budget, hipStream_t s);
+
+// Provenance of component coefficients, for the backward:
+// (target cls, target idx, source cls, source idx, site string) -> list of
+// (integral entry, d coefficient / d entry).
+using CompKey = std::tuple<int, int, int, int, uint64_t>;
+struct CompProv {
+  std::map<CompKey, double> coef;                                  // total coefficients
+  std::map<CompKey, std::vector<std::pair<int64_t, double>>> prov;  // integral dependence
+};
+
 // Builds the operators of sites [0, b+1) from those of [0, b) and site b.
+// When rec is given, every component and its integral dependence is recorded.
 std::unique_ptr<Env> left_start(const Mps& m, hipStream_t s);
 std::unique_ptr<Env> right_start(const Mps& m, hipStream_t s);
 std::unique_ptr<Env> grow_left(const Problem& P, const Mps& m, const Env& old, DevBuf& scratch,
-                               hipStream_t s);
+                               hipStream_t s, CompProv* rec = nullptr);
 std::unique_ptr<Env> grow_right(const Problem& P, const Mps& m, const Env& old, DevBuf& scratch,
-                                hipStream_t s);
+                                hipStream_t s, CompProv* rec = nullptr);
 
 // ---- sigma ----------------------------------------------------------------------
 // psi of window (i, i+1) is stored right-sector-major: for each sector r of
 // bond i+2 the rows (l, n1, n2) with Q_l + Q_n1 + Q_n2 = Q_r in ascending
 // order form a dense M_r x d_r row-major matrix Psi_r; the Psi_r follow each
 // other in ascending r.
+//
+// Internally the sigma works on a padded copy: every (l, n1, n2) row group
+// starts at a multiple of 8 rows and holds pad8(d_l) rows (zero padding),
+// and rows have pad8(d_r) columns.  PsiT_r (d_r x rows_pad) is its transpose.
 struct PsiLayout {
   std::vector<int64_t> rows_of;  // M_r
-  std::vector<int64_t> off;      // element offset of Psi_r
+  std::vector<int64_t> off;      // element offset of Psi_r (API layout)
   std::vector<std::map<std::pair<int, int>, int64_t>> row_of;  // per r: (l, 4*n1+n2) -> row
   int64_t size = 0;
+  // padded copy
+  std::vector<int64_t> rows_pad, off_pad, offT;
+  std::vector<int> ld;
+  std::vector<std::map<std::pair<int, int>, int64_t>> row_pad_of;
+  int64_t size_pad = 0, sizeT = 0;
   void build(const Bond& bl, const Bond& br);
+};
+
+// Row-group copy task: rows x cols from src (row stride sld) to dst (dld),
+// optionally transposed (dst[c][r] = src[r][c]).
+struct CopyTask {
+  const double* src;
+  double* dst;
+  int32_t rows, cols, sld, dld;
 };
 
 struct OpView {
@@ -225,6 +277,8 @@ struct SigmaPair {
   Mat16 y;   // site matrix, coefficient folded in
   int ypar;  // fermion parity of the site string
   bool pinned = false;  // always FP64 (block Hamiltonians: energy-sized diagonals)
+  int lsrc = 0;         // 0: stored left operator, 1: window partial sum
+  OpRef lref;           // the left operator in the left block or in psums
 };
 
 // The sigma schedule is kept precision-agnostic: operands are (buffer id,
@@ -265,7 +319,12 @@ struct SigmaPlan {
   std::vector<int> zpar;
   std::vector<SigmaPair> pairs;
   std::vector<PlanBuf> bufs;
-  int buf_psi = -1, buf_sig = -1, buf_ws = -1;
+  int buf_psi = -1, buf_sig = -1, buf_ws = -1, buf_psit = -1;
+  DevBuf pack_tasks, unpack_tasks, trans_tasks;  // CopyTask arrays
+  int n_pack = 0, n_trans = 0;
+  std::vector<CopyTask> pack_host, unpack_host;  // API side as byte offsets
+  const double* bound_psi = nullptr;
+  const double* bound_sigma = nullptr;
   std::vector<AStage> s1, s2;  // per chunk (pairs not pinned to FP64)
   AStage p1, p2;               // pairs pinned to FP64 (one chunk)
   // materialised descriptors
@@ -278,12 +337,23 @@ struct SigmaPlan {
   double flops = 0;            // algorithmic FLOPs of one sigma
   double flops_stage1 = 0, flops_stage2 = 0;
   int64_t ws_doubles = 0;
+  // kept for the backward
+  std::vector<OpRef> zrefs;    // right-block operator of each zops entry
+  bool record = false;
+  using PsumKey = std::pair<uint64_t, uint64_t>;  // (site string, right string)
+  std::map<PsumKey, std::map<std::pair<int, int>, std::vector<std::pair<int64_t, double>>>> psum_prov;
+  std::vector<std::pair<PsumKey, OpRef>> wkeys;    // partial sum of each key
+  std::map<int, int> w_src_cls;                    // psums class -> left class of its sources
 };
 
 // Plans the sigma of window (i, i+1) from the left block at bond i and the
 // right block at bond i+2 (both renormalised).
+// With record set, the plan also keeps the integral dependence of the
+// partial-sum coefficients (for the backward).
 std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env& L, const Env& R,
-                                      int64_t ws_budget_doubles, hipStream_t s);
+                                      int64_t ws_budget_doubles, hipStream_t s, bool record = false);
+// Copies psi (API layout) into the plan's padded psi buffer and its transpose.
+void plan_load_psi(SigmaPlan& plan, const double* psi, hipStream_t s);
 // sigma = H_eff psi (device pointers, right-sector-major psi layout).
 // precision: 0 FP64, 1 BF16, 2 split-BF16x3.
 void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision, hipStream_t s);

@@ -94,6 +94,9 @@ void launch_multidot(double* out, const double* X, int64_t ldx, int nv, const do
 // y = sum_j c[j] * X[j] (+ beta * y)
 void launch_lincomb(double* y, const double* X, int64_t ldx, int nv, const double* c,
                     int64_t n, double beta, hipStream_t s);
+// block copies (one workgroup per task), optionally transposing
+struct CopyTask;
+void launch_copy_tasks(const CopyTask* tasks, int ntasks, bool transpose, hipStream_t s);
 // scatter-add rows: dst[idx[r]] += src[r]   (rows of length n)
 void launch_row_scatter_add(double* dst, const double* src, const int64_t* dst_off, int nrows,
                             int64_t n, hipStream_t s);

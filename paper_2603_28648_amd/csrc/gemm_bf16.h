@@ -9,6 +9,8 @@ namespace dmrg {
 
 enum : int { kOutBf16 = 0, kOutF64 = 1 };
 
+// NT operands: A row-major m x k (stride lda), B stored n x k (stride ldb),
+// rows 16-byte aligned and zero-padded in k to a multiple of 8.
 struct GemmSegB {
   const uint16_t* a;  // bf16 hi; the lo part (split mode) is at a + alo
   const uint16_t* b;
@@ -26,16 +28,17 @@ struct GemmTileB {
 struct GemmBatchB {
   std::vector<GemmSegB> segs;
   std::vector<GemmTileB> tiles;
+  static constexpr int TM = 128, TN = 64;  // tile of the NT kernel
   void add_problem(void* c, int64_t clo, int ldc, int m, int n, size_t s0, size_t s1, int beta) {
     if (m <= 0 || n <= 0 || s1 <= s0) return;
-    for (int r = 0; r < m; r += kTileM)
-      for (int q = 0; q < n; q += kTileN) {
+    for (int r = 0; r < m; r += TM)
+      for (int q = 0; q < n; q += TN) {
         GemmTileB t;
         t.c = c;
         t.clo = clo;
         t.ldc = ldc;
-        t.m = std::min(kTileM, m - r);
-        t.n = std::min(kTileN, n - q);
+        t.m = std::min(TM, m - r);
+        t.n = std::min(TN, n - q);
         t.row0 = r;
         t.col0 = q;
         t.seg_begin = (int32_t)s0;

@@ -5,6 +5,7 @@
 
 #include "gemm.h"
 #include "davidson.h"
+#include "engine.h"
 
 namespace dmrg {
 
@@ -275,10 +276,25 @@ void launch_row_scatter_add(double* dst, const double* src, const int64_t* dst_o
   DMRG_HIP(hipGetLastError());
 }
 
+__global__ void k_copy_tasks(const CopyTask* tasks, int transpose) {
+  const CopyTask t = tasks[blockIdx.x];
+  const int64_t n = (int64_t)t.rows * t.cols;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int r = (int)(e / t.cols), c = (int)(e % t.cols);
+    if (transpose) t.dst[(int64_t)c * t.dld + r] = t.src[(int64_t)r * t.sld + c];
+    else t.dst[(int64_t)r * t.dld + c] = t.src[(int64_t)r * t.sld + c];
+  }
+}
+void launch_copy_tasks(const CopyTask* tasks, int ntasks, bool transpose, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(k_copy_tasks, dim3(ntasks), dim3(256), 0, s, tasks, (int)transpose);
+  DMRG_HIP(hipGetLastError());
+}
+
 // ---- Davidson helpers --------------------------------------------------------
 __global__ void k_extract_diag(const DiagTask* tasks) {
   const DiagTask t = tasks[blockIdx.x];
-  for (int i = threadIdx.x; i < t.d; i += blockDim.x) t.dst[i] = t.src[(int64_t)i * (t.d + 1)];
+  for (int i = threadIdx.x; i < t.d; i += blockDim.x) t.dst[i] = t.src[(int64_t)i * (t.ld + 1)];
 }
 void launch_extract_diag(const DiagTask* tasks, int ntasks, hipStream_t s) {
   for (int off = 0; off < ntasks; off += 1 << 30) {

@@ -1,7 +1,7 @@
 // gfx950 BF16 MFMA grouped GEMM for the mixed-precision sigma.
 //
-// Same task model as the FP64 kernel (one workgroup per 64x64 output tile,
-// a list of segments accumulated in registers).  Operands are BF16; with
+// Same task model as the FP64 kernel (one workgroup per output tile, a list
+// of segments accumulated in registers).  Operands are BF16; with
 // X3 every operand x is split as x ~ hi + lo (hi = bf16(x), lo =
 // bf16(x - hi)) and the product uses hi*hi + hi*lo + lo*hi (16-bit
 // effective mantissa).  Each segment is accumulated in FP32 by the MFMA
@@ -30,108 +30,164 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rn(float f) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-constexpr int kBK = 32;            // k per slab (one 16x16x32 MFMA)
-constexpr int kBLd = kBK + 8;      // LDS row stride in bf16 (16-byte aligned, skewed)
+// NT products only: A row-major (m x k, row stride lda), B stored n x k (row
+// stride ldb); both k-contiguous, 16-byte aligned rows with zero padding up
+// to a multiple of 8 in k (the layouts of the sigma guarantee this).
+//
+// Workgroup tile 128 x 64, four waves as 2 x 2, each wave 64 x 32 = 4 x 2
+// MFMA 16x16x32 blocks.  k advances in slabs of 32 through two LDS buffers;
+// the next slab's global loads are issued before the current slab's MFMAs
+// (register prefetch), so one barrier per slab suffices.
+constexpr int kBM = 128, kBN = 64, kBK = 32, kBLd = kBK + 8;
 
-// MFMA 16x16x32 bf16 (wave64): lane l supplies A[l%16][8*(l/16) .. +7] and
-// B[8*(l/16) .. +7][l%16]; accumulator element v holds D[4*(l/16)+v][l%16].
+struct __attribute__((aligned(16))) V8 { uint32_t x, y, z, w; };
+
+template <bool X3>
+struct SlabRegs {
+  V8 a[2][X3 ? 2 : 1];  // two 16-byte vectors of A per thread (hi, lo)
+  V8 b[1][X3 ? 2 : 1];  // one of B
+};
+
+__device__ __forceinline__ V8 ld16(const uint16_t* p) { return *reinterpret_cast<const V8*>(p); }
+
+template <bool X3>
+__device__ __forceinline__ void load_slab(SlabRegs<X3>& R, const GemmSegB& g, const GemmTileB& t,
+                                          int k0, int kpad, int tid) {
+  // A: 128 rows x 4 vectors; thread covers vectors tid and tid + 256
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int v = tid + 256 * q;
+    const int row = v >> 2, kk = k0 + 8 * (v & 3);
+    V8 hi{0, 0, 0, 0}, lo{0, 0, 0, 0};
+    if (row < t.m && kk < kpad) {
+      const int64_t idx = ((int64_t)t.row0 + row) * g.lda + kk;
+      hi = ld16(g.a + idx);
+      if (X3) lo = ld16(g.a + g.alo + idx);
+    }
+    R.a[q][0] = hi;
+    if (X3) R.a[q][X3 ? 1 : 0] = lo;
+  }
+  {
+    const int row = tid >> 2, kk = k0 + 8 * (tid & 3);
+    V8 hi{0, 0, 0, 0}, lo{0, 0, 0, 0};
+    if (row < t.n && kk < kpad) {
+      const int64_t idx = ((int64_t)t.col0 + row) * g.ldb + kk;
+      hi = ld16(g.b + idx);
+      if (X3) lo = ld16(g.b + g.blo + idx);
+    }
+    R.b[0][0] = hi;
+    if (X3) R.b[0][X3 ? 1 : 0] = lo;
+  }
+}
+
 template <bool X3, int OUT, int ROLE>
-__global__ __launch_bounds__(256) void k_gemm_bf16(const GemmTileB* __restrict__ tiles,
-                                                    const GemmSegB* __restrict__ segs) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[X3 ? 2 : 1][kTileM][kBLd];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[X3 ? 2 : 1][kTileN][kBLd];
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16(const GemmTileB* __restrict__ tiles,
+                                                       const GemmSegB* __restrict__ segs) {
+  constexpr int NP = X3 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][NP][kBM][kBLd];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][NP][kBN][kBLd];
   const GemmTileB t = tiles[blockIdx.x];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
-  double acc[2][2][4];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
+  double acc[4][2][4];
+  f32x4 sacc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      sacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
       for (int v = 0; v < 4; ++v) acc[a][b][v] = 0.0;
+    }
 
-  for (int s = t.seg_begin; s < t.seg_end; ++s) {
-    const GemmSegB g = segs[s];
-    const bool ta = g.flags & kTransA, tb = g.flags & kTransB;
-    f32x4 sacc[2][2];
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) sacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.k; k0 += kBK) {
-      // stage A (64 x 32) and B (32 x 64, stored [j][k]) for hi (and lo)
+  int s = t.seg_begin;
+  if (s < t.seg_end) {
+    GemmSegB g = segs[s];
+    int kpad = (g.k + 7) & ~7;
+    int k0 = 0;
+    SlabRegs<X3> R;
+    load_slab<X3>(R, g, t, 0, kpad, tid);
+    int buf = 0;
+    auto store = [&](int bb) {
 #pragma unroll
-      for (int r = 0; r < (kTileM * kBK) / 256; ++r) {
-        const int e = r * 256 + tid;
-        int i, kk;
-        if (!ta) { i = e / kBK; kk = e % kBK; }
-        else { kk = e / kTileM; i = e % kTileM; }
-        const int gk = k0 + kk;
-        uint16_t hi = 0, lo = 0;
-        if (i < t.m && gk < g.k) {
-          const int64_t gi = (int64_t)t.row0 + i;
-          const int64_t idx = ta ? (int64_t)gk * g.lda + gi : gi * g.lda + gk;
-          hi = g.a[idx];
-          if (X3) lo = g.a[idx + g.alo];
+      for (int q = 0; q < 2; ++q) {
+        const int v = tid + 256 * q;
+        const int row = v >> 2, kc = 8 * (v & 3);
+        *reinterpret_cast<V8*>(&As[bb][0][row][kc]) = R.a[q][0];
+        if (X3) *reinterpret_cast<V8*>(&As[bb][NP - 1][row][kc]) = R.a[q][NP - 1];
+      }
+      const int row = tid >> 2, kc = 8 * (tid & 3);
+      *reinterpret_cast<V8*>(&Bs[bb][0][row][kc]) = R.b[0][0];
+      if (X3) *reinterpret_cast<V8*>(&Bs[bb][NP - 1][row][kc]) = R.b[0][NP - 1];
+    };
+    store(0);
+    __syncthreads();
+    for (;;) {
+      // coordinates of the next slab
+      int ns = s, nk = k0 + kBK, nkpad = kpad;
+      GemmSegB ng = g;
+      if (nk >= kpad) {
+        ns = s + 1;
+        nk = 0;
+        if (ns < t.seg_end) {
+          ng = segs[ns];
+          nkpad = (ng.k + 7) & ~7;
         }
-        As[0][i][kk] = hi;
-        if (X3) As[X3 ? 1 : 0][i][kk] = lo;
       }
+      const bool has_next = ns < t.seg_end;
+      if (has_next) load_slab<X3>(R, ng, t, nk, nkpad, tid);
+      // MFMAs on the current slab
+      bf16x8 ah[4], bh[2];
 #pragma unroll
-      for (int r = 0; r < (kTileN * kBK) / 256; ++r) {
-        const int e = r * 256 + tid;
-        int j, kk;
-        if (!tb) { kk = e / kTileN; j = e % kTileN; }
-        else { j = e / kBK; kk = e % kBK; }
-        const int gk = k0 + kk;
-        uint16_t hi = 0, lo = 0;
-        if (j < t.n && gk < g.k) {
-          const int64_t gj = (int64_t)t.col0 + j;
-          const int64_t idx = tb ? gj * g.ldb + gk : (int64_t)gk * g.ldb + gj;
-          hi = g.b[idx];
-          if (X3) lo = g.b[idx + g.blo];
-        }
-        Bs[0][j][kk] = hi;
-        if (X3) Bs[X3 ? 1 : 0][j][kk] = lo;
-      }
-      __syncthreads();
-      bf16x8 ah[2], bh[2];
+      for (int x = 0; x < 4; ++x) ah[x] = *reinterpret_cast<const bf16x8*>(&As[buf][0][wm + 16 * x + lr][8 * lk]);
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
-        ah[x] = *reinterpret_cast<const bf16x8*>(&As[0][wm + 16 * x + lr][8 * lk]);
-        bh[x] = *reinterpret_cast<const bf16x8*>(&Bs[0][wn + 16 * x + lr][8 * lk]);
-      }
+      for (int x = 0; x < 2; ++x) bh[x] = *reinterpret_cast<const bf16x8*>(&Bs[buf][0][wn + 16 * x + lr][8 * lk]);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], sacc[a][b], 0, 0, 0);
       if (X3) {
-        bf16x8 al[2], bl[2];
+        bf16x8 al[4], bl[2];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          al[x] = *reinterpret_cast<const bf16x8*>(&As[X3 ? 1 : 0][wm + 16 * x + lr][8 * lk]);
-          bl[x] = *reinterpret_cast<const bf16x8*>(&Bs[X3 ? 1 : 0][wn + 16 * x + lr][8 * lk]);
-        }
+        for (int x = 0; x < 4; ++x) al[x] = *reinterpret_cast<const bf16x8*>(&As[buf][NP - 1][wm + 16 * x + lr][8 * lk]);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int x = 0; x < 2; ++x) bl[x] = *reinterpret_cast<const bf16x8*>(&Bs[buf][NP - 1][wn + 16 * x + lr][8 * lk]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
             sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], sacc[a][b], 0, 0, 0);
             sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], sacc[a][b], 0, 0, 0);
           }
       }
+      if (ns != s) {
+        // segment finished: scale by alpha and flush into the FP64 accumulator
+        const double al = g.alpha;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[a][b][v] += al * (double)sacc[a][b][v];
+            sacc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+      if (!has_next) break;
+      store(buf ^ 1);
       __syncthreads();
+      buf ^= 1;
+      s = ns;
+      k0 = nk;
+      g = ng;
+      kpad = nkpad;
     }
-    const double al = g.alpha;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[a][b][v] += al * (double)sacc[a][b][v];
   }
 
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
