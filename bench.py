@@ -1,16 +1,21 @@
 """Benchmark of the two-site DMRG sigma step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config cas54_36|cas22_22]
-                    [--precision fp64|bf16|bf16x3] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--config cas54_36|cas54_36_sz2|cas22_22]
+                    [--precision bf16x3|bf16|fp64] [--fp64-steps K64] [--dav-iters I]
+                    [--no-cpu-baseline]
 
 Workload (default): CAS(54,36)-shaped active space (36 orbitals, 54
 electrons, 2Sz = 0), bond dimension D = 4096, middle window (17, 18),
 synthetic integrals (seed 36) and a converged-like random MPS (seed 1036).
 Operators are built once (dmrg_build_ops, untimed); a timed step is one
-sigma = H_eff psi on the resident psi.  The JSON line reports algorithmic
-sigma TFLOP/s, the roofline of the grouped-GEMM kernel measured with HIP
-events on the library's stream, and the CPU oracle timed on a bounded sample
-of the same contraction on the host cores.
+sigma = H_eff psi on the resident psi in the mixed precision (split-BF16x3
+MFMA, block Hamiltonians in FP64) unless --precision says otherwise.  The
+JSON line reports algorithmic sigma TFLOP/s; beside it the FP64 sigma of the
+same psi (time, relative difference, Rayleigh-quotient difference), the
+Davidson step time with the mixed ladder, the roofline of the dominant
+grouped-GEMM kernel from HIP events the library records around each launch
+on its stream, and the CPU oracle timed on a bounded sample of the same
+contraction on the host cores.
 """
 import argparse
 import json
@@ -76,12 +81,30 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="cas54_36", choices=sorted(CONFIGS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "bf16", "bf16x3"])
+    ap.add_argument("--precision", default="bf16x3", choices=["fp64", "bf16", "bf16x3"],
+                    help="precision of the timed sigma steps (the mixed path by default)")
+    ap.add_argument("--fp64-steps", type=int, default=3,
+                    help="FP64 sigma steps timed beside the headline precision (0: skip)")
+    ap.add_argument("--dav-iters", type=int, default=4,
+                    help="Davidson iterations timed with the mixed ladder (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-terms", type=int, default=30)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device-to-device copy of MB megabytes, 3 times "
+                         "(reference for the HBM byte counters), then exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each": 8 * n, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sigma "
               "would shard over Hamiltonian terms with one all-reduce of sigma per "
@@ -110,32 +133,75 @@ def main():
     log(f"[bench] build_ops {t_build:.1f}s, {info['n_pairs']} pairs, "
         f"{info['operator_bytes'] / 1e9:.1f} GB operators, {info['flops']:.3e} flop/sigma")
     psi = torch.from_numpy(pack_psi(m.bonds, i, m.psi)).to("cuda")
+    psi /= torch.linalg.norm(psi)
     out = torch.empty_like(psi)
+    ref = torch.empty_like(psi)
     torch.cuda.synchronize()
+
+    def timed_sigma(prec, steps, warmup, target):
+        """Median event time of `steps` sigma calls on the library stream, and
+        the library's per-launch kernel times over the same calls."""
+        with torch.cuda.stream(stream):
+            for _ in range(warmup):
+                ctx.sigma(psi, target, prec)
+        stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        ctx.sigma_timing(1)
+        tw = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for k in range(steps):
+                ev[k][0].record(stream)
+                ctx.sigma(psi, target, prec)
+                ev[k][1].record(stream)
+        stream.synchronize()
+        tw = time.perf_counter() - tw
+        kt = ctx.sigma_timing(0)
+        times = np.array([a.elapsed_time(b) for a, b in ev])
+        return times, kt, tw
+
+    # FP64 reference sigma (also the comparison the metric asks for)
+    fp64 = None
     with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            ctx.sigma(psi, out, args.precision)
+        ctx.sigma(psi, ref, "fp64")
     stream.synchronize()
-    torch.cuda.synchronize()
-    # timed region: events on the library's stream around every step
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    t_wall = time.perf_counter()
-    with torch.cuda.stream(stream):
-        for k in range(args.steps):
-            ev[k][0].record(stream)
-            ctx.sigma(psi, out, args.precision)
-            ev[k][1].record(stream)
-    stream.synchronize()
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall
-    times = np.array([a.elapsed_time(b) for a, b in ev])  # ms
+    if args.fp64_steps > 0 and args.precision != "fp64":
+        t64, kt64, _ = timed_sigma("fp64", args.fp64_steps, 0, ref)
+        fp64 = {"ms": float(np.median(t64)), "tflops": info["flops"] / (np.median(t64) * 1e-3) / 1e12}
+        log(f"[bench] sigma fp64: median {fp64['ms']:.2f} ms ({fp64['tflops']:.2f} TFLOP/s)")
+    times, kt, t_wall = timed_sigma(args.precision, args.steps, args.warmup, out)
     ms = float(np.median(times))
-    energy = float(torch.dot(psi, out).item())
+    e_ref = float(torch.dot(psi, ref).item())
+    e_mix = float(torch.dot(psi, out).item())
+    rel = float((torch.linalg.norm(out - ref) / torch.linalg.norm(ref)).item())
     log(f"[bench] sigma {args.precision}: median {ms:.2f} ms, min {times.min():.2f}, "
-        f"max {times.max():.2f}; <psi|H|psi> = {energy:.10f}")
+        f"max {times.max():.2f}; <psi|H|psi> = {e_mix:.10f} (FP64 {e_ref:.10f}); "
+        f"|dsigma|/|sigma| = {rel:.2e}")
     tflops = info["flops"] / (ms * 1e-3) / 1e12
-    launches = 2 * info["n_chunks"]
+    # dominant kernel: the grouped GEMM of the main stages (stage 1 + stage 2)
+    n_launch = kt["launches_stage1"] + kt["launches_stage2"]
+    ms_kernel = (kt["ms_stage1"] + kt["ms_stage2"]) / max(1, n_launch)
+    flops_launch = (kt["flops_stage1"] + kt["flops_stage2"]) * kt["calls"] / max(1, n_launch)
+    achieved = flops_launch / (ms_kernel * 1e-3) / 1e12
+    kname = "k_gemm_f64" if args.precision == "fp64" else "k_gemm_bf16"
+    log(f"[bench] {kname}: {n_launch} launches, avg {ms_kernel:.3f} ms, stage1 "
+        f"{kt['ms_stage1'] / kt['calls']:.1f} ms + stage2 {kt['ms_stage2'] / kt['calls']:.1f} ms + "
+        f"pinned FP64 {kt['ms_pinned'] / kt['calls']:.1f} ms per sigma; {achieved:.1f} TFLOP/s")
+    # Davidson step time with the mixed ladder (FP64 vectors and subspace)
+    dav = None
+    if args.dav_iters > 0:
+        x = psi.clone()
+        with torch.cuda.stream(stream):
+            r = ctx.davidson(x, tol=1e-12, max_iter=args.dav_iters,
+                             ladder=((args.precision, 1e-12), ("fp64", None)))
+        stream.synchronize()
+        n_sig = sum(r["n_sigma"].values())
+        other = (r["time_ms"] - r["sigma_ms"]) / max(1, n_sig)
+        dav = {"iterations": r["iterations"], "time_ms": r["time_ms"], "sigma_calls": r["n_sigma"],
+               "step_ms": ms + other, "non_sigma_ms_per_step": other, "energy": r["energy"],
+               "residual": r["residual"]}
+        log(f"[bench] davidson {r['iterations']} iterations: {r['time_ms']:.0f} ms total, "
+            f"{other:.2f} ms non-sigma per step -> step {ms + other:.1f} ms")
     cpu = None
     if not args.no_cpu_baseline:
         t_cpu, n_s, n_all, per = cpu_baseline(m, args.cpu_terms)
@@ -148,6 +214,7 @@ def main():
                          f"D={D} enlarged sectors, {per:.2f} s/term scaled to all terms; FLOPs "
                          f"counted as the library's algorithmic sigma FLOPs"}
         log(f"[bench] cpu oracle: {per:.2f} s/term -> {t_cpu:.0f} s/sigma")
+    peak = PEAK_TFLOPS[args.precision]
     res = {
         "metric": METRIC,
         "value": tflops,
@@ -164,14 +231,19 @@ def main():
         "config": {"workload": f"{args.config}: K={K} N={N} 2Sz={tsz} D={D} window=({i},{i + 1})",
                    "psi_size": m.psi_size(), "sigma_flops": info["flops"],
                    "pairs": info["n_pairs"], "precision": args.precision,
-                   "build_ops_s": round(t_build, 2), "energy_rayleigh": energy,
-                   "wall_s_timed": round(t_wall, 3)},
-        "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_TFLOPS[args.precision],
-                     "unit": "TFLOP/s", "frac": tflops / PEAK_TFLOPS[args.precision],
-                     "traffic": None,
-                     "kernel": "k_gemm_f64 (stage 1 + stage 2 launches of one sigma)",
-                     "launches_per_step": launches,
-                     "avg_launch_ms": ms / launches},
+                   "build_ops_s": round(t_build, 2), "wall_s_timed": round(t_wall, 3),
+                   "rayleigh": e_mix, "rayleigh_fp64": e_ref, "rayleigh_diff": e_mix - e_ref,
+                   "sigma_rel_err_vs_fp64": rel,
+                   "fp64_sigma_ms": fp64["ms"] if fp64 else None,
+                   "fp64_sigma_tflops": fp64["tflops"] if fp64 else None,
+                   "speedup_vs_fp64": fp64["ms"] / ms if fp64 else None,
+                   "davidson": dav},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"{kname} (stage-1 and stage-2 grouped-GEMM launches)",
+                     "launches_per_step": n_launch / max(1, kt["calls"]),
+                     "avg_launch_ms": ms_kernel,
+                     "hw_tflops": achieved * (3 if args.precision == "bf16x3" else 1)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -133,6 +133,21 @@ typedef struct {
 } dmrg_sigma_info;
 dmrg_status dmrg_sigma_get_info(dmrg_ctx ctx, int32_t precision, dmrg_sigma_info* out);
 
+/* Kernel timing of dmrg_sigma: HIP events recorded on the context stream
+ * around every grouped-GEMM launch of a sigma (diagnostic; off by default).
+ * mode 1 resets the totals and starts timing, 0 stops, -1 leaves it as is.
+ * out (may be NULL) receives the totals of the calls timed so far; reading
+ * them synchronises the stream.  Times are summed over calls. */
+typedef struct {
+  int32_t calls;              /* sigma calls timed */
+  int32_t launches_stage1;    /* stage-1 launches (psi x right operators), summed */
+  int32_t launches_stage2;    /* stage-2 launches (left operators x stage 1) */
+  int32_t launches_pinned;    /* FP64 launches of the block-Hamiltonian pairs */
+  double ms_stage1, ms_stage2, ms_pinned;
+  double flops_stage1, flops_stage2, flops_pinned;  /* algorithmic FLOPs of one call */
+} dmrg_sigma_times;
+dmrg_status dmrg_sigma_timing(dmrg_ctx ctx, int32_t mode, dmrg_sigma_times* out);
+
 /* Davidson solve for the lowest eigenpair of H_eff at the current window
  * (Davidson 1975, diagonal preconditioner, thick restart to the Ritz vector;
  * the Numerical-procedure section's eigensolver tolerance is a residual

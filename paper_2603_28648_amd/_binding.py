@@ -60,6 +60,14 @@ class DavidsonOpts(ctypes.Structure):
                 ("precondition", ctypes.c_int32), ("restart", ctypes.c_int32)]
 
 
+class SigmaTimes(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int32), ("launches_stage1", ctypes.c_int32),
+                ("launches_stage2", ctypes.c_int32), ("launches_pinned", ctypes.c_int32),
+                ("ms_stage1", ctypes.c_double), ("ms_stage2", ctypes.c_double),
+                ("ms_pinned", ctypes.c_double), ("flops_stage1", ctypes.c_double),
+                ("flops_stage2", ctypes.c_double), ("flops_pinned", ctypes.c_double)]
+
+
 class DavidsonStats(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("residual", ctypes.c_double),
                 ("time_ms", ctypes.c_double), ("sigma_ms", ctypes.c_double),
@@ -84,6 +92,7 @@ EXPORTS = {
                                        ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int32)]),
     "dmrg_get_psi": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dmrg_sigma_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SigmaTimes)]),
     "dmrg_sigma_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_debug_diag": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -196,6 +205,13 @@ class Context:
         p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self._check(self.lib.dmrg_sigma(self.h, _dev_ptr(psi), _dev_ptr(out), p), self.h)
         return out
+
+    def sigma_timing(self, mode=-1):
+        """Kernel timing of sigma calls (mode 1: reset and start, 0: stop,
+        -1: keep); returns the totals so far as a dict."""
+        t = SigmaTimes()
+        self._check(self.lib.dmrg_sigma_timing(self.h, int(mode), ctypes.byref(t)), self.h)
+        return {k: getattr(t, k) for k, _ in SigmaTimes._fields_}
 
     def sigma_backward(self, psi, sigma_bar=None, dh=None, deri=None):
         """Gradient of <sigma_bar, H_eff psi> with respect to h (K x K) and

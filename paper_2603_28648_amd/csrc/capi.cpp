@@ -412,6 +412,33 @@ dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* 
   return kOk;
 }
 
+dmrg_status dmrg_sigma_timing(dmrg_ctx c, int32_t mode, dmrg_sigma_times* out) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->plan, kErrState, "sigma_timing: call dmrg_build_ops first");
+    DMRG_REQUIRE(mode >= -1 && mode <= 1, kErrInvalidArg, "sigma_timing: mode must be -1, 0 or 1");
+    SigmaPlan& p = *c->plan;
+    SigmaTiming& t = p.timing;
+    t.collect(c->stream);
+    if (mode == 1) t.reset();
+    if (mode >= 0) t.on = mode == 1;
+    if (out) {
+      std::memset(out, 0, sizeof(*out));
+      out->calls = t.calls;
+      out->launches_stage1 = t.launches[1];
+      out->launches_stage2 = t.launches[2];
+      out->launches_pinned = t.launches[3];
+      out->ms_stage1 = t.ms[1];
+      out->ms_stage2 = t.ms[2];
+      out->ms_pinned = t.ms[3];
+      for (auto& a : p.s1) out->flops_stage1 += a.flops;
+      for (auto& a : p.s2) out->flops_stage2 += a.flops;
+      out->flops_pinned = p.p1.flops + p.p2.flops;
+    }
+    return kOk;
+  });
+}
+
 dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const double* a,
                             int32_t lda, int32_t trans_a, const double* b, int32_t ldb,
                             int32_t trans_b, double* cc, int32_t ldc, double alpha, int32_t beta,

@@ -982,6 +982,41 @@ static void bind_tasks(const std::vector<CopyTask>& host, DevBuf& dev, const dou
   bound = key;
 }
 
+hipEvent_t SigmaTiming::get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  DMRG_HIP(hipEventCreate(&e));
+  return e;
+}
+void SigmaTiming::collect(hipStream_t s) {
+  if (pending.empty()) return;
+  DMRG_HIP(hipStreamSynchronize(s));
+  for (auto& p : pending) {
+    float t = 0;
+    DMRG_HIP(hipEventElapsedTime(&t, p.second.first, p.second.second));
+    ms[p.first] += t;
+    launches[p.first] += 1;
+    pool.push_back(p.second.first);
+    pool.push_back(p.second.second);
+  }
+  pending.clear();
+}
+void SigmaTiming::reset() {
+  for (int k = 0; k < 4; ++k) { ms[k] = 0; launches[k] = 0; }
+  calls = 0;
+}
+SigmaTiming::~SigmaTiming() {
+  for (auto& p : pending) {
+    (void)hipEventDestroy(p.second.first);
+    (void)hipEventDestroy(p.second.second);
+  }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
 void plan_load_psi(SigmaPlan& plan, const double* psi, hipStream_t s) {
   if (plan.bound_psi != psi) DMRG_HIP(hipStreamSynchronize(s));
   bind_tasks(plan.pack_host, plan.pack_tasks, psi, nullptr, true, plan.bound_psi);
@@ -997,13 +1032,27 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
   bind_tasks(plan.unpack_host, plan.unpack_tasks, nullptr, sigma, false, plan.bound_sigma);
   plan_load_psi(plan, psi, s);
   launch_fill(S.f64, 0.0, S.n, s);
+  SigmaTiming& tm = plan.timing;
+  // runs one launch, bracketed by events when timing is on
+  auto timed = [&](int role, auto&& launch) {
+    if (!tm.on) {
+      launch();
+      return;
+    }
+    hipEvent_t a = tm.get(), b = tm.get();
+    DMRG_HIP(hipEventRecord(a, s));
+    launch();
+    DMRG_HIP(hipEventRecord(b, s));
+    tm.record(role, a, b);
+  };
+  if (tm.on) ++tm.calls;
   // pairs pinned to FP64 first (they reuse the stage-1 workspace)
-  launch_gemm_f64(plan.f64_p1, s, 1);
-  launch_gemm_f64(plan.f64_p2, s, 2);
+  timed(3, [&] { launch_gemm_f64(plan.f64_p1, s, 1); });
+  timed(3, [&] { launch_gemm_f64(plan.f64_p2, s, 2); });
   if (precision == 0) {
     for (size_t c = 0; c < plan.f64_s1.size(); ++c) {
-      launch_gemm_f64(plan.f64_s1[c], s, 1);
-      launch_gemm_f64(plan.f64_s2[c], s, 2);
+      timed(1, [&] { launch_gemm_f64(plan.f64_s1[c], s, 1); });
+      timed(2, [&] { launch_gemm_f64(plan.f64_s2[c], s, 2); });
     }
   } else {
     prepare_bf16(plan, s);
@@ -1011,8 +1060,8 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
     launch_split_bf16(T.bf.as<uint16_t>(), T.f64, T.n, s);
     const bool x3 = precision == 2;
     for (size_t c = 0; c < plan.bf_s1.size(); ++c) {
-      launch_gemm_bf16(plan.bf_s1[c], x3, kOutBf16, 1, s);
-      launch_gemm_bf16(plan.bf_s2[c], x3, kOutF64, 2, s);
+      timed(1, [&] { launch_gemm_bf16(plan.bf_s1[c], x3, kOutBf16, 1, s); });
+      timed(2, [&] { launch_gemm_bf16(plan.bf_s2[c], x3, kOutF64, 2, s); });
     }
   }
   launch_copy_tasks(plan.unpack_tasks.as<CopyTask>(), plan.n_pack, false, s);

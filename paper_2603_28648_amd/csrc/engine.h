@@ -311,8 +311,29 @@ struct PlanBuf {
   bool is_operator = false;
 };
 
+// Optional kernel timing of run_sigma: HIP events recorded on the launch
+// stream around every grouped-GEMM launch (role 1 / 2: main stages, role 3:
+// the FP64 launches of the pinned pairs).
+struct SigmaTiming {
+  bool on = false;
+  int calls = 0;
+  double ms[4] = {0, 0, 0, 0};  // by role
+  int launches[4] = {0, 0, 0, 0};
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (role, begin/end)
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get();
+  void record(int role, hipEvent_t a, hipEvent_t b) { pending.push_back({role, {a, b}}); }
+  void collect(hipStream_t s);  // waits for the stream, folds pending events into ms
+  void reset();
+  SigmaTiming() = default;
+  SigmaTiming(const SigmaTiming&) = delete;
+  SigmaTiming& operator=(const SigmaTiming&) = delete;
+  ~SigmaTiming();
+};
+
 struct SigmaPlan {
   int window = -1;
+  SigmaTiming timing;
   PsiLayout psi;
   std::unique_ptr<Env> psums;  // window partial sums of left operators
   std::vector<OpView> zops;    // distinct right operators

@@ -96,10 +96,11 @@ def test_backward_equals_fci_rdms_with_exact_bonds(ctx):
     h, eri, m = case(10, 10, 0, 1024, 4)
     n = lib_load(ctx, h, eri, m)
     psi = _dev(pack_psi(m.bonds, m.window, m.psi))
-    e, st = ctx.davidson(psi, tol=1e-10, max_iter=400)
+    r = ctx.davidson(psi, tol=1e-10, max_iter=400)
     torch.cuda.synchronize()
+    e = r["energy"]
     w, v, space = fci(10, 10, 0, h, eri)
-    print(f"  E_dmrg={e:.12f} E_fci={w[0]:.12f} residual={st.residual:.2e}", flush=True)
+    print(f"  E_dmrg={e:.12f} E_fci={w[0]:.12f} residual={r['residual']:.2e}", flush=True)
     assert abs(e - w[0]) < 1e-9
     dh, deri = _backward(ctx, psi.cpu().numpy())
     g, G = rdm12(space, v[:, 0], v[:, 0])
