@@ -171,6 +171,12 @@ def main():
         log(f"[bench] sigma fp64: median {fp64['ms']:.2f} ms ({fp64['tflops']:.2f} TFLOP/s)")
     times, kt, t_wall = timed_sigma(args.precision, args.steps, args.warmup, out)
     ms = float(np.median(times))
+    info2 = ctx.sigma_info(args.precision)  # after the first mixed sigma: autotuned launch configuration
+    tuned = {"stage1": info2["bf_config_stage1"], "stage2": info2["bf_config_stage2"],
+             "tune_ms": info2["tune_ms"]}
+    if args.precision != "fp64":
+        log(f"[bench] BF16 launch configuration (shape + 16*grouping + 256*segment order): "
+            f"stage 1 {tuned['stage1']}, stage 2 {tuned['stage2']}, autotuned in {tuned['tune_ms']:.0f} ms")
     e_ref = float(torch.dot(psi, ref).item())
     e_mix = float(torch.dot(psi, out).item())
     rel = float((torch.linalg.norm(out - ref) / torch.linalg.norm(ref)).item())
@@ -237,6 +243,7 @@ def main():
                    "fp64_sigma_ms": fp64["ms"] if fp64 else None,
                    "fp64_sigma_tflops": fp64["tflops"] if fp64 else None,
                    "speedup_vs_fp64": fp64["ms"] / ms if fp64 else None,
+                   "bf16_launch_config": tuned if args.precision != "fp64" else None,
                    "davidson": dav},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,

@@ -130,6 +130,13 @@ typedef struct {
   int32_t pad;
   double flops_stage1;   /* psi x right operators */
   double flops_stage2;   /* left operators x stage-1 results */
+  /* BF16 launch configuration per stage, chosen by the autotuner on the
+   * first mixed-precision sigma of the window (until then the default):
+   * tile shape (0: 128x64, 1: 64x64, 2: 64x128) + 16 * tile grouping
+   * (0: per output problem, 1: per operand-sharing key) + 256 * segment
+   * order (1: sorted by operand) */
+  int32_t bf_config_stage1, bf_config_stage2;
+  double tune_ms;        /* time the autotuner took (0 if it did not run) */
 } dmrg_sigma_info;
 dmrg_status dmrg_sigma_get_info(dmrg_ctx ctx, int32_t precision, dmrg_sigma_info* out);
 

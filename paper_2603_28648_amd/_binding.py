@@ -50,7 +50,8 @@ class SigmaInfo(ctypes.Structure):
                 ("n_stage2_segments", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("operator_bytes", ctypes.c_int64), ("n_chunks", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("flops_stage1", ctypes.c_double),
-                ("flops_stage2", ctypes.c_double)]
+                ("flops_stage2", ctypes.c_double), ("bf_config_stage1", ctypes.c_int32),
+                ("bf_config_stage2", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
 
 
 class DavidsonOpts(ctypes.Structure):

@@ -1,6 +1,8 @@
 // C ABI of the library (see include/dmrg.h).  Arguments are validated on the
 // host before any device work; exceptions never cross the ABI.
+#include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -405,6 +407,10 @@ dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* 
     out->n_stage2_segments += (int64_t)g.nsegs;
   }
   out->workspace_bytes = p.ws_doubles * 8;
+  auto code = [](const BfChoice& c) { return c.shape + 16 * c.order + 256 * c.sort_a; };
+  out->bf_config_stage1 = code(p.bf_choice[0]);
+  out->bf_config_stage2 = code(p.bf_choice[1]);
+  out->tune_ms = p.tune_ms;
   out->n_chunks = (int32_t)p.s1.size();
   for (auto& kv : c->left) out->operator_bytes += (int64_t)kv.second->bytes();
   for (auto& kv : c->right) out->operator_bytes += (int64_t)kv.second->bytes();
@@ -480,6 +486,7 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const d
     launch_split_bf16(abf.as<uint16_t>(), da.as<double>(), na, c->stream);
     launch_split_bf16(bbf.as<uint16_t>(), db.as<double>(), nb, c->stream);
     GemmBatchB bt;
+    if (const char* sh = std::getenv("DMRG_BF16_SHAPE")) bt.shape = std::max(0, std::min(kNumShapes - 1, std::atoi(sh)));
     bt.segs.push_back({abf.as<uint16_t>(), bbf.as<uint16_t>(), na, nb, kp, kp, k, kTransB, alpha});
     bt.add_problem(cc, 0, ldc, m, n, 0, 1, beta);
     DevGemmB d;

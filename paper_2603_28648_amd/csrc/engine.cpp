@@ -24,7 +24,9 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <set>
 #include <tuple>
@@ -517,6 +519,15 @@ void PsiLayout::build(const Bond& bl, const Bond& br) {
   }
 }
 
+// Problem indices of a stage ordered by locality key (stable).
+static std::vector<size_t> by_key(const AStage& A) {
+  std::vector<size_t> idx(A.probs.size());
+  for (size_t q = 0; q < idx.size(); ++q) idx[q] = q;
+  std::stable_sort(idx.begin(), idx.end(),
+                   [&](size_t x, size_t y) { return A.probs[x].key < A.probs[y].key; });
+  return idx;
+}
+
 std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env& L, const Env& R,
                                       int64_t ws_budget, hipStream_t s, bool record) {
   const int i = L.bond;
@@ -823,13 +834,14 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
           const double alpha = (plan->zpar[z] && (br.q[r].n & 1)) ? -1.0 : 1.0;
           const int64_t s0 = (int64_t)st1.segs.size();
           st1.segs.push_back({ref_of(Z.data + blk.off), {BP, ps.off_pad[r]}, blk.ld, ps.ld[r], br.d[r], kTransB, alpha});
-          st1.probs.push_back({{BW, off}, (int)ps.rows_pad[r], br.d[rp], (int)ps.rows_pad[r], s0, s0 + 1, 0});
+          // key: the psi sector, so that Psi_r stays in one XCD's L2
+          st1.probs.push_back({{BW, off}, (int)ps.rows_pad[r], br.d[rp], (int)ps.rows_pad[r], s0, s0 + 1, 0, r});
           st1.flops += 2.0 * ps.rows_of[r] * br.d[rp] * br.d[r];
           off += ps.rows_pad[r] * br.d[rp];
         }
       }
       std::map<std::tuple<int, int64_t>, std::vector<ASeg>> outs;
-      std::map<std::tuple<int, int64_t>, int> out_m;
+      std::map<std::tuple<int, int64_t>, int> out_m, out_l;
       auto zin = [&](int z) { return z == -1 ? ci == 0 : (z >= z0 && z < z1); };
       for (auto& pz : pairs_of_z) {
         if (!zin(pz.first)) continue;
@@ -867,6 +879,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
                 outs[ok].push_back({{lref.buf, lref.off + lb.off}, bref, lb.ld, (int)ps.rows_pad[r], lb.dc,
                                     kTransB, yv * sg});
                 out_m[ok] = lb.dr;
+                out_l[ok] = lp;
               }
             }
         }
@@ -880,8 +893,9 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
           st2.segs.push_back(sgm);
           st2.flops += 2.0 * mrows * br.d[rp] * sgm.k;
         }
+        // key: the left sector of the output rows
         st2.probs.push_back({{BS, ps.off_pad[rp] + row * ps.ld[rp]}, ps.ld[rp], mrows, br.d[rp], s0,
-                             (int64_t)st2.segs.size(), 1});
+                             (int64_t)st2.segs.size(), 1, out_l[o.first]});
       }
       plan->flops += st1.flops + st2.flops;
       plan->flops_stage1 += st1.flops;
@@ -904,11 +918,17 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     for (auto& g : A.segs)
       b.segs.push_back({plan->bufs[g.a.buf].f64 + g.a.off, plan->bufs[g.b.buf].f64 + g.b.off,
                         g.lda, g.ldb, g.k, g.flags, g.alpha});
-    for (auto& pb : A.probs)
+    std::vector<int> keys;
+    for (size_t q : by_key(A)) {
+      const AProb& pb = A.probs[q];
       b.add_problem(plan->bufs[pb.c.buf].f64 + pb.c.off, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
                     (size_t)pb.s1, pb.beta);
-    std::stable_sort(b.tiles.begin(), b.tiles.end(), [](const GemmTile& x, const GemmTile& y) {
-      return (x.seg_end - x.seg_begin) > (y.seg_end - y.seg_begin);
+      keys.resize(b.tiles.size(), pb.key);
+    }
+    xcd_order(b.tiles, keys, [&](const GemmTile& t) {
+      double c = 0;
+      for (int k = t.seg_begin; k < t.seg_end; ++k) c += b.segs[k].k + 32;
+      return c;
     });
     upload_gemm(b, out);
   };
@@ -924,8 +944,128 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
   return plan;
 }
 
+// BF16 descriptors of one stage (all chunks) for one launch configuration:
+// tile shape, locality grouping of the tiles (0: each problem its own group,
+// 1: the problems of one key together) and segment order (1: each problem's
+// segments sorted by their A operand).
+static void build_bf_stage(SigmaPlan& plan, int stage, const BfChoice& ch, std::vector<DevGemmB>& out) {
+  auto bfp = [&](const BufRef& r) { return plan.bufs[r.buf].bf.as<uint16_t>() + r.off; };
+  const std::vector<AStage>& st = stage == 1 ? plan.s1 : plan.s2;
+  out.clear();
+  out.reserve(st.size());
+  for (const AStage& A : st) {
+    GemmBatchB b;
+    b.shape = ch.shape;
+    b.segs.reserve(A.segs.size());
+    std::vector<size_t> order(A.probs.size());
+    for (size_t q = 0; q < order.size(); ++q) order[q] = q;
+    if (ch.order == 1) order = by_key(A);
+    std::vector<int> keys;
+    std::vector<int64_t> perm;
+    for (size_t q : order) {
+      const AProb& pb = A.probs[q];
+      const size_t s0 = b.segs.size();
+      perm.clear();
+      for (int64_t k = pb.s0; k < pb.s1; ++k) perm.push_back(k);
+      if (ch.sort_a)
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) {
+          return std::tie(A.segs[x].a.buf, A.segs[x].a.off) < std::tie(A.segs[y].a.buf, A.segs[y].a.off);
+        });
+      for (int64_t k : perm) {
+        const ASeg& g = A.segs[k];
+        DMRG_REQUIRE(g.flags == kTransB && g.lda % 8 == 0 && g.ldb % 8 == 0 && g.a.off % 8 == 0 &&
+                         g.b.off % 8 == 0,
+                     kErrState, "prepare_bf16: segment is not an aligned NT product");
+        b.segs.push_back({bfp(g.a), bfp(g.b), plan.bufs[g.a.buf].n, plan.bufs[g.b.buf].n, g.lda,
+                          g.ldb, g.k, g.flags, g.alpha});
+      }
+      if (stage == 1)
+        b.add_problem(bfp(pb.c), plan.bufs[pb.c.buf].n, pb.ldc, pb.m, pb.n, s0, b.segs.size(), 0);
+      else
+        b.add_problem(plan.bufs[pb.c.buf].f64 + pb.c.off, 0, pb.ldc, pb.m, pb.n, s0, b.segs.size(),
+                      pb.beta);
+      keys.resize(b.tiles.size(), ch.order == 1 ? pb.key : (int)q);
+    }
+    auto tcost = [&](const GemmTileB& t) {
+      double c = 0;
+      for (int k = t.seg_begin; k < t.seg_end; ++k) c += b.segs[k].k + 32;
+      return c;
+    };
+    if (std::getenv("DMRG_VERBOSE") && std::atoi(std::getenv("DMRG_VERBOSE")) > 1) {
+      double tot = 0, mx = 0;
+      for (auto& t : b.tiles) {
+        const double c = tcost(t);
+        tot += c;
+        mx = std::max(mx, c);
+      }
+      fprintf(stderr, "[dmrg] stage %d chunk %zu: %zu tiles, %zu segments, max tile %.3g of total %.3g (x%.1f of a 512-slot share)\n",
+              stage, out.size(), b.tiles.size(), b.segs.size(), mx, tot, mx / std::max(1.0, tot / 512));
+    }
+    xcd_order(b.tiles, keys, tcost);
+    out.emplace_back();
+    upload_gemm_bf16(b, out.back());
+  }
+}
+
+static void launch_bf_stage(const std::vector<DevGemmB>& d, int stage, bool x3, hipStream_t s) {
+  for (const DevGemmB& g : d) launch_gemm_bf16(g, x3, stage == 1 ? kOutBf16 : kOutF64, stage, s);
+}
+
+// Event time (ms) of one stage over all chunks, best of reps after a warm-up.
+// The launches write the stage's real outputs (workspace, sigma buffer), which
+// every sigma overwrites or clears first.
+static double time_bf_stage(const std::vector<DevGemmB>& d, int stage, bool x3, hipStream_t s, int reps) {
+  hipEvent_t a, b;
+  DMRG_HIP(hipEventCreate(&a));
+  DMRG_HIP(hipEventCreate(&b));
+  double best = 1e300;
+  launch_bf_stage(d, stage, x3, s);
+  for (int r = 0; r < reps; ++r) {
+    DMRG_HIP(hipEventRecord(a, s));
+    launch_bf_stage(d, stage, x3, s);
+    DMRG_HIP(hipEventRecord(b, s));
+    DMRG_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    DMRG_HIP(hipEventElapsedTime(&ms, a, b));
+    best = std::min(best, (double)ms);
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+// Autotuner of the BF16 launch configuration: per stage, first the tile
+// shape (with per-problem grouping, schedule order), then the grouping and
+// segment order for that shape; every candidate is timed on this plan's own
+// launches.  Small plans keep the default (their launches are too short to
+// time reliably and the tuning would cost more than it saves).
+static void autotune_bf16(SigmaPlan& plan, hipStream_t s) {
+  const bool x3 = true;  // the mixed path's main precision
+  const double t0 = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  for (int stage = 1; stage <= 2; ++stage) {
+    BfChoice best;
+    double tbest = 1e300;
+    std::vector<DevGemmB> d;
+    auto trial = [&](const BfChoice& c) {
+      build_bf_stage(plan, stage, c, d);
+      const double t = time_bf_stage(d, stage, x3, s, 2);
+      plan.tune_log.push_back({stage, c, t});
+      if (t < tbest) { tbest = t; best = c; }
+    };
+    for (int sh = 0; sh < kNumShapes; ++sh) trial(BfChoice{sh, 0, 0});
+    const int sh = best.shape;
+    trial(BfChoice{sh, 1, 0});
+    if (stage == 2) {
+      trial(BfChoice{sh, 0, 1});
+      trial(BfChoice{sh, 1, 1});
+    }
+    plan.bf_choice[stage - 1] = best;
+  }
+  plan.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count() - t0;
+}
+
 // BF16 hi/lo copies of every operator, the psi and workspace buffers, and the
-// BF16 descriptors (built once per plan, on first use).
+// BF16 descriptors (built once per plan, on first use, after the autotuner).
 void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
   if (plan.bf_ready) return;
   for (size_t k = 0; k < plan.bufs.size(); ++k) {
@@ -933,35 +1073,26 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
     if ((int)k == plan.buf_sig) continue;
     b.bf.alloc((size_t)std::max<int64_t>(1, 2 * b.n) * sizeof(uint16_t));
     if (b.is_operator) launch_split_bf16(b.bf.as<uint16_t>(), b.f64, b.n, s);
+    else launch_fill(reinterpret_cast<double*>(b.bf.p), 0.0, (int64_t)(b.bf.bytes / sizeof(double)), s);
   }
-  auto bfp = [&](const BufRef& r) { return plan.bufs[r.buf].bf.as<uint16_t>() + r.off; };
-  for (size_t c = 0; c < plan.s1.size(); ++c) {
-    for (int stage = 1; stage <= 2; ++stage) {
-      const AStage& A = stage == 1 ? plan.s1[c] : plan.s2[c];
-      GemmBatchB b;
-      b.segs.reserve(A.segs.size());
-      for (auto& g : A.segs) {
-        DMRG_REQUIRE(g.flags == kTransB && g.lda % 8 == 0 && g.ldb % 8 == 0 && g.a.off % 8 == 0 &&
-                         g.b.off % 8 == 0,
-                     kErrState, "prepare_bf16: segment is not an aligned NT product");
-        b.segs.push_back({bfp(g.a), bfp(g.b), plan.bufs[g.a.buf].n, plan.bufs[g.b.buf].n, g.lda,
-                          g.ldb, g.k, g.flags, g.alpha});
-      }
-      for (auto& pb : A.probs) {
-        if (stage == 1)
-          b.add_problem(bfp(pb.c), plan.bufs[pb.c.buf].n, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
-                        (size_t)pb.s1, 0);
-        else
-          b.add_problem(plan.bufs[pb.c.buf].f64 + pb.c.off, 0, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
-                        (size_t)pb.s1, pb.beta);
-      }
-      std::stable_sort(b.tiles.begin(), b.tiles.end(), [](const GemmTileB& x, const GemmTileB& y) {
-        return (x.seg_end - x.seg_begin) > (y.seg_end - y.seg_begin);
-      });
-      (stage == 1 ? plan.bf_s1 : plan.bf_s2).emplace_back();
-      upload_gemm_bf16(b, (stage == 1 ? plan.bf_s1 : plan.bf_s2).back());
-    }
+  // DMRG_BF16_SHAPE=0|1|2 fixes the tile shape of both stages (tests of each
+  // kernel variant); otherwise DMRG_AUTOTUNE=0|1 switches the autotuner off or
+  // on (default: on for plans above 5e10 FLOP per sigma).
+  const char* fixed = std::getenv("DMRG_BF16_SHAPE");
+  const char* env = std::getenv("DMRG_AUTOTUNE");
+  if (fixed) {
+    const int sh = std::atoi(fixed);
+    DMRG_REQUIRE(sh >= 0 && sh < kNumShapes, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0, 1, 2 or 3");
+    plan.bf_choice[0].shape = plan.bf_choice[1].shape = sh;
+  } else if (env ? std::atoi(env) != 0 : plan.flops > 5e10) {
+    autotune_bf16(plan, s);
+    if (std::getenv("DMRG_VERBOSE"))
+      for (auto& e : plan.tune_log)
+        fprintf(stderr, "[dmrg] autotune stage %d shape %d order %d sort %d: %.2f ms\n", e.stage,
+                e.choice.shape, e.choice.order, e.choice.sort_a, e.ms);
   }
+  build_bf_stage(plan, 1, plan.bf_choice[0], plan.bf_s1);
+  build_bf_stage(plan, 2, plan.bf_choice[1], plan.bf_s2);
   DMRG_HIP(hipStreamSynchronize(s));
   plan.bf_ready = true;
 }

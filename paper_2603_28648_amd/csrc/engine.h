@@ -297,6 +297,7 @@ struct AProb {
   int32_t ldc, m, n;
   int64_t s0, s1;
   int32_t beta;
+  int32_t key = 0;  // locality group: problems of one key run on one XCD
 };
 struct AStage {
   std::vector<ASeg> segs;
@@ -331,8 +332,23 @@ struct SigmaTiming {
   ~SigmaTiming();
 };
 
+// Launch configuration of the BF16 stages (chosen by the autotuner).
+struct BfChoice {
+  int shape = kShape128x64;  // tile shape
+  int order = 0;             // 0: per-problem XCD groups, 1: groups by locality key
+  int sort_a = 0;            // 1: segments of a problem sorted by their A operand
+};
+struct TuneEntry {
+  int stage;
+  BfChoice choice;
+  double ms;
+};
+
 struct SigmaPlan {
   int window = -1;
+  BfChoice bf_choice[2];            // stage 1, stage 2
+  std::vector<TuneEntry> tune_log;  // autotuner trials
+  double tune_ms = 0;
   SigmaTiming timing;
   PsiLayout psi;
   std::unique_ptr<Env> psums;  // window partial sums of left operators

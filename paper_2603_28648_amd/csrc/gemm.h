@@ -6,6 +6,7 @@
 // same tile, so all contributions to a tile accumulate in registers and the
 // tile is written once.  No two tiles of one launch may overlap in C.
 #pragma once
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -67,6 +68,71 @@ struct GemmBatch {
   }
   void clear() { segs.clear(); tiles.clear(); flops = 0; }
 };
+
+// MI355X hands the workgroups of a launch to its 8 XCDs round-robin by block
+// index (block b runs on XCD b mod 8), and each XCD has its own L2.
+constexpr int kXcds = 8;
+
+// Reorders a launch's tiles for L2 locality.  key[t] names a locality group
+// (tiles of one group share operands: the caller emits them consecutively,
+// problem by problem, each problem's tiles row by row).  A group runs on one
+// XCD, in emission order; groups are spread over the XCDs longest first onto
+// the least loaded one, a group larger than a quarter of an XCD's share being
+// cut at problem boundaries into pieces of about that size (cost(tile)
+// estimates a tile's time).  Queues are interleaved so that block b takes the
+// next tile of XCD b mod 8's queue; shorter queues are padded with empty
+// tiles (m = 0), which the kernels skip.
+template <class Tile, class Cost>
+void xcd_order(std::vector<Tile>& tiles, const std::vector<int>& key, Cost&& cost) {
+  struct Group {
+    size_t t0, t1;
+    double c;
+  };
+  const size_t nt = tiles.size();
+  std::vector<double> tc(nt);
+  double total = 0;
+  for (size_t i = 0; i < nt; ++i) total += (tc[i] = cost(tiles[i]));
+  const double cap = std::max(1.0, total / (4.0 * kXcds));
+  auto same_problem = [&](size_t a, size_t b) {
+    return tiles[a].c == tiles[b].c && tiles[a].seg_begin == tiles[b].seg_begin &&
+           tiles[a].seg_end == tiles[b].seg_end;
+  };
+  std::vector<Group> groups;
+  for (size_t i = 0; i < nt;) {
+    size_t j = i;
+    double c = 0;
+    // extend over whole problems of the same key up to the cap
+    while (j < nt && key[j] == key[i]) {
+      size_t e = j + 1;
+      while (e < nt && same_problem(e, j)) ++e;
+      double pc = 0;
+      for (size_t k = j; k < e; ++k) pc += tc[k];
+      if (j > i && c + pc > cap) break;
+      c += pc;
+      j = e;
+    }
+    groups.push_back({i, j, c});
+    i = j;
+  }
+  std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) { return a.c > b.c; });
+  std::vector<std::vector<size_t>> queue(kXcds);
+  double load[kXcds] = {};
+  for (const Group& g : groups) {
+    int x = 0;
+    for (int y = 1; y < kXcds; ++y)
+      if (load[y] < load[x]) x = y;
+    for (size_t k = g.t0; k < g.t1; ++k) queue[x].push_back(k);
+    load[x] += g.c;
+  }
+  size_t len = 0;
+  for (auto& q : queue) len = std::max(len, q.size());
+  Tile empty{};
+  std::vector<Tile> out;
+  out.reserve(len * kXcds);
+  for (size_t i = 0; i < len; ++i)
+    for (int x = 0; x < kXcds; ++x) out.push_back(i < queue[x].size() ? tiles[queue[x][i]] : empty);
+  tiles.swap(out);
+}
 
 // Launch (stream-ordered).  dev_scratch holds the uploaded descriptors; it is
 // grown as needed; the call returns after the launch is enqueued and the

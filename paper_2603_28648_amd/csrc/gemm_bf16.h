@@ -8,6 +8,10 @@
 namespace dmrg {
 
 enum : int { kOutBf16 = 0, kOutF64 = 1 };
+// Workgroup tile shapes of the BF16 kernel (rows x columns of the output).
+enum : int { kShape128x64 = 0, kShape64x64 = 1, kShape64x128 = 2, kShape128x128 = 3, kNumShapes = 4 };
+inline int shape_rows(int s) { return (s == kShape128x64 || s == kShape128x128) ? 128 : 64; }
+inline int shape_cols(int s) { return (s == kShape64x128 || s == kShape128x128) ? 128 : 64; }
 
 // NT operands: A row-major m x k (stride lda), B stored n x k (stride ldb),
 // rows 16-byte aligned and zero-padded in k to a multiple of 8.
@@ -28,9 +32,10 @@ struct GemmTileB {
 struct GemmBatchB {
   std::vector<GemmSegB> segs;
   std::vector<GemmTileB> tiles;
-  static constexpr int TM = 128, TN = 64;  // tile of the NT kernel
+  int shape = kShape128x64;  // tile of the NT kernel
   void add_problem(void* c, int64_t clo, int ldc, int m, int n, size_t s0, size_t s1, int beta) {
     if (m <= 0 || n <= 0 || s1 <= s0) return;
+    const int TM = shape_rows(shape), TN = shape_cols(shape);
     for (int r = 0; r < m; r += TM)
       for (int q = 0; q < n; q += TN) {
         GemmTileB t;
@@ -54,6 +59,7 @@ struct DevGemmB {
   GemmSegB* segs = nullptr;
   GemmTileB* tiles = nullptr;
   size_t ntiles = 0, nsegs = 0;
+  int shape = kShape128x64;
 };
 
 void upload_gemm_bf16(const GemmBatchB& b, DevGemmB& d);

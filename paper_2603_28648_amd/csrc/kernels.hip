@@ -29,6 +29,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
   __shared__ double As[kTK][kTileM + 1];
   __shared__ double Bs[kTK][kTileN + 1];
   const GemmTile t = tiles[blockIdx.x];
+  if (t.m <= 0) return;  // padding tile of the XCD-ordered launch
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;

@@ -35,9 +35,11 @@ BF_TOL = {"bf16": 1.6e-2, "bf16x3": 1.5e-4}
 @pytest.mark.parametrize("m,n,k", SHAPES)
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
-def test_gemm_bf16_matches_reference(ctx, m, n, k, ta, tb, prec):
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])  # 128x64, 64x64, 64x128, 128x128 workgroup tiles
+def test_gemm_bf16_matches_reference(ctx, monkeypatch, m, n, k, ta, tb, prec, tile):
     import torch
-    print(f"gemm_{prec} m={m} n={n} k={k} ta={ta} tb={tb}", flush=True)
+    monkeypatch.setenv("DMRG_BF16_SHAPE", tile)
+    print(f"gemm_{prec} tile={tile} m={m} n={n} k={k} ta={ta} tb={tb}", flush=True)
     g = torch.Generator().manual_seed(7 + m * 1000 + n * 10 + k)
     A = torch.randn(m, k, generator=g, dtype=torch.float64)
     B = torch.randn(k, n, generator=g, dtype=torch.float64)

@@ -75,9 +75,11 @@ def test_sigma_repeat_is_bitwise_deterministic(ctx):
 
 
 @pytest.mark.parametrize("K,N,tsz,D,i", [(8, 8, 0, 64, 3), (12, 12, 0, 256, 5), (10, 9, 1, 200, 2)])
-def test_mixed_sigma_error_vs_fp64(ctx, K, N, tsz, D, i):
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3"])  # 128x64, 64x64, 64x128, 128x128 workgroup tiles
+def test_mixed_sigma_error_vs_fp64(ctx, monkeypatch, K, N, tsz, D, i, tile):
     """BF16 and split-BF16x3 sigma against the FP64 sigma of the same plan."""
-    print(f"mixed sigma K={K} D={D} window={i}", flush=True)
+    monkeypatch.setenv("DMRG_BF16_SHAPE", tile)
+    print(f"mixed sigma K={K} D={D} window={i} tile={tile}", flush=True)
     h, eri, m = case(K, N, tsz, D, i)
     n = lib_load(ctx, h, eri, m)
     x = np.random.default_rng(5).normal(size=n)
@@ -91,3 +93,25 @@ def test_mixed_sigma_error_vs_fp64(ctx, K, N, tsz, D, i):
     assert e16 < 2e-2
     assert e48 < 1e-4
     assert e48 < e16 / 20
+
+
+def test_autotuned_mixed_sigma(ctx, monkeypatch):
+    """The autotuner times every candidate launch configuration on the plan's
+    own launches (which write the real buffers) and keeps the fastest; the
+    sigma afterwards is still correct and bitwise repeatable."""
+    monkeypatch.delenv("DMRG_BF16_SHAPE", raising=False)
+    monkeypatch.setenv("DMRG_AUTOTUNE", "1")
+    print("autotuned mixed sigma K=14 D=300 window=6", flush=True)
+    h, eri, m = case(14, 14, 0, 300, 6)
+    n = lib_load(ctx, h, eri, m)
+    x = np.random.default_rng(6).normal(size=n)
+    x /= np.linalg.norm(x)
+    s64 = lib_sigma_flat(ctx, x, "fp64")
+    s48 = lib_sigma_flat(ctx, x, "bf16x3")
+    info = ctx.sigma_info("bf16x3")
+    print(f"  tuned in {info['tune_ms']:.1f} ms: stage1 config {info['bf_config_stage1']}, "
+          f"stage2 config {info['bf_config_stage2']}", flush=True)
+    assert info["tune_ms"] > 0
+    e48 = np.linalg.norm(s48 - s64) / np.linalg.norm(s64)
+    assert e48 < 1e-4
+    assert np.array_equal(s48, lib_sigma_flat(ctx, x, "bf16x3"))
