@@ -1082,7 +1082,7 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
   const char* env = std::getenv("DMRG_AUTOTUNE");
   if (fixed) {
     const int sh = std::atoi(fixed);
-    DMRG_REQUIRE(sh >= 0 && sh < kNumShapes, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0, 1, 2 or 3");
+    DMRG_REQUIRE(sh >= 0 && sh < kNumShapes, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0 to 4");
     plan.bf_choice[0].shape = plan.bf_choice[1].shape = sh;
   } else if (env ? std::atoi(env) != 0 : plan.flops > 5e10) {
     autotune_bf16(plan, s);

@@ -58,13 +58,15 @@ constexpr int kFlush = 8;  // segments accumulated in FP32 between FP64 flushes
 // Per tile shape: the 64-row and 128 x 64 tiles keep an FP64 register
 // accumulator (FP32 MFMA partials flushed into it every kFlush segments)
 // and three LDS stages; the 128 x 128 tile gives each wave a 64 x 64 block
-// (twice the operand reuse per LDS byte of a 64 x 32 block), accumulates in
-// FP32 only (its registers go to the larger block) and has two LDS stages.
-template <int BM, int BN>
+// (twice the operand reuse per LDS byte of a 64 x 32 block) and accumulates
+// in FP32 only (its registers go to the larger block), with two LDS stages
+// (two workgroups per CU) or three (one slab more in flight, one workgroup
+// per CU in split-BF16x3).
+template <int BM, int BN, int ST>
 struct TileCfg {
   static constexpr bool ACC64 = !(BM == 128 && BN == 128);
-  static constexpr int STAGES = ACC64 ? 3 : 2;
-  static constexpr int MIN_BLOCKS = (BM * BN <= 4096) ? 3 : 2;
+  static constexpr int STAGES = ST;
+  static constexpr int MIN_BLOCKS = (BM * BN <= 4096) ? 3 : (ST == 3 && !ACC64 ? 1 : 2);
 };
 
 __device__ __attribute__((aligned(16))) uint32_t g_zero16[4];  // 16 zero bytes (static storage)
@@ -99,43 +101,55 @@ struct SlabShape {
   static_assert(BLOCKS % 4 == 0, "slab blocks split over four waves");
 };
 
-// Issues the loads of one slab (segment g, k offset k0) into the buffer buf.
+// Per-lane sources of the slab loads: load j of a lane covers row
+// 16 (wave PER_WAVE + j) + lane / 4 of the slab and the k-chunk
+// (lane % 4) ^ sw(row); base[j] points at that row and chunk of the current
+// segment (k offset 0), or is null for a row outside the tile.
 template <bool X3, int BM, int BN>
-__device__ __forceinline__ void issue_slab(uint16_t* buf, const GemmSegB& g, const GemmTileB& t,
-                                           int k0, int kpad, int wave, int lane) {
+struct LaneLoads {
   using SS = SlabShape<X3, BM, BN>;
-  const uint16_t* zero = reinterpret_cast<const uint16_t*>(g_zero16);
-  const int slot = lane & 3;
+  const uint16_t* base[SS::PER_WAVE];
+  int c8[SS::PER_WAVE];  // k offset of the lane's chunk
+
+  __device__ __forceinline__ void segment(const GemmSegB& g, const GemmTileB& t, int wave, int lane) {
 #pragma unroll
-  for (int j = 0; j < SS::PER_WAVE; ++j) {
-    const int b = wave * SS::PER_WAVE + j;  // wave-uniform block
-    const int rr = 16 * b + (lane >> 2);
-    const uint16_t* src = zero;
-    if (rr < SS::NP * BM) {
-      const int row = rr & (BM - 1);
-      const int kk = k0 + 8 * (slot ^ swz(row));
-      if (row < t.m && kk < kpad)
-        src = g.a + (rr >= BM ? g.alo : 0) + ((int64_t)t.row0 + row) * g.lda + kk;
-    } else {
-      const int r2 = rr - SS::NP * BM;
-      const int row = r2 & (BN - 1);
-      const int kk = k0 + 8 * (slot ^ swz(row));
-      if (row < t.n && kk < kpad)
-        src = g.b + (r2 >= BN ? g.blo : 0) + ((int64_t)t.col0 + row) * g.ldb + kk;
+    for (int j = 0; j < SS::PER_WAVE; ++j) {
+      const int rr = 16 * (wave * SS::PER_WAVE + j) + (lane >> 2);
+      if (rr < SS::NP * BM) {
+        const int row = rr & (BM - 1);
+        c8[j] = 8 * ((lane & 3) ^ swz(row));
+        base[j] = row < t.m ? g.a + (rr >= BM ? g.alo : 0) + ((int64_t)t.row0 + row) * g.lda + c8[j]
+                            : nullptr;
+      } else {
+        const int r2 = rr - SS::NP * BM;
+        const int row = r2 & (BN - 1);
+        c8[j] = 8 * ((lane & 3) ^ swz(row));
+        base[j] = row < t.n ? g.b + (r2 >= BN ? g.blo : 0) + ((int64_t)t.col0 + row) * g.ldb + c8[j]
+                            : nullptr;
+      }
     }
-    __builtin_amdgcn_global_load_lds(src, buf + 512 * b, 16, 0, 0);
   }
-}
+  // Issues the loads of the slab at k offset k0 (segment padded to kpad)
+  // into the buffer buf; chunks outside the operand read the zero buffer.
+  __device__ __forceinline__ void issue(uint16_t* buf, int k0, int kpad, int wave) const {
+    const uint16_t* zero = reinterpret_cast<const uint16_t*>(g_zero16);
+#pragma unroll
+    for (int j = 0; j < SS::PER_WAVE; ++j) {
+      const uint16_t* src = (base[j] && k0 + c8[j] < kpad) ? base[j] + k0 : zero;
+      __builtin_amdgcn_global_load_lds(src, buf + 512 * (wave * SS::PER_WAVE + j), 16, 0, 0);
+    }
+  }
+};
 
 __device__ __forceinline__ bf16x8 frag(const uint16_t* part, int row, int q) {
   return *reinterpret_cast<const bf16x8*>(part + row * 32 + 8 * (q ^ swz(row)));
 }
 
-template <bool X3, int OUT, int ROLE, int BM, int BN>
-__global__ __launch_bounds__(256, (TileCfg<BM, BN>::MIN_BLOCKS)) void k_gemm_bf16(
+template <bool X3, int OUT, int ROLE, int BM, int BN, int ST>
+__global__ __launch_bounds__(256, (TileCfg<BM, BN, ST>::MIN_BLOCKS)) void k_gemm_bf16(
     const GemmTileB* __restrict__ tiles, const GemmSegB* __restrict__ segs) {
   using SS = SlabShape<X3, BM, BN>;
-  using TC = TileCfg<BM, BN>;
+  using TC = TileCfg<BM, BN, ST>;
   constexpr int NP = SS::NP;
   constexpr int kStages = TC::STAGES;
   constexpr int FM = BM / 32, FN = BN / 32;  // 16x16 blocks of a wave
@@ -186,8 +200,10 @@ __global__ __launch_bounds__(256, (TileCfg<BM, BN>::MIN_BLOCKS)) void k_gemm_bf1
     GemmSegB cg = pg;
     int ckpad = pkpad;
     int issued = 0, done = 0;  // slabs
+    LaneLoads<X3, BM, BN> ld;
+    ld.segment(pg, t, wave, lane);
     auto produce = [&]() {
-      issue_slab<X3, BM, BN>(&smem[issued % kStages][0], pg, t, pk0, pkpad, wave, lane);
+      ld.issue(&smem[issued % kStages][0], pk0, pkpad, wave);
       ++issued;
       pk0 += kBK;
       if (pk0 >= pkpad) {
@@ -195,6 +211,7 @@ __global__ __launch_bounds__(256, (TileCfg<BM, BN>::MIN_BLOCKS)) void k_gemm_bf1
         if (++ps < t.seg_end) {
           pg = segs[ps];
           pkpad = (pg.k + 7) & ~7;
+          ld.segment(pg, t, wave, lane);
         }
       }
     };
@@ -320,10 +337,28 @@ __global__ __launch_bounds__(256, (TileCfg<BM, BN>::MIN_BLOCKS)) void k_gemm_bf1
   }
 }
 
-template <int BM, int BN>
+// Every variant is instantiated explicitly: it forces both the device code
+// and the host launch stub of each one into this object.
+#define DMRG_INST_SHAPE(BM, BN, ST)                                                                 \
+  template __global__ void k_gemm_bf16<true, kOutF64, 2, BM, BN, ST>(const GemmTileB*, const GemmSegB*);  \
+  template __global__ void k_gemm_bf16<true, kOutF64, 0, BM, BN, ST>(const GemmTileB*, const GemmSegB*);  \
+  template __global__ void k_gemm_bf16<true, kOutBf16, 1, BM, BN, ST>(const GemmTileB*, const GemmSegB*); \
+  template __global__ void k_gemm_bf16<true, kOutBf16, 0, BM, BN, ST>(const GemmTileB*, const GemmSegB*); \
+  template __global__ void k_gemm_bf16<false, kOutF64, 2, BM, BN, ST>(const GemmTileB*, const GemmSegB*); \
+  template __global__ void k_gemm_bf16<false, kOutF64, 0, BM, BN, ST>(const GemmTileB*, const GemmSegB*); \
+  template __global__ void k_gemm_bf16<false, kOutBf16, 1, BM, BN, ST>(const GemmTileB*, const GemmSegB*); \
+  template __global__ void k_gemm_bf16<false, kOutBf16, 0, BM, BN, ST>(const GemmTileB*, const GemmSegB*);
+DMRG_INST_SHAPE(128, 64, 3)
+DMRG_INST_SHAPE(64, 64, 3)
+DMRG_INST_SHAPE(64, 128, 3)
+DMRG_INST_SHAPE(128, 128, 2)
+DMRG_INST_SHAPE(128, 128, 3)
+#undef DMRG_INST_SHAPE
+
+template <int BM, int BN, int ST>
 static void launch_shape(const GemmTileB* tl, unsigned cnt, const GemmSegB* sg, bool x3, int out,
                          int role, hipStream_t s) {
-#define DMRG_LB(X, O, R) hipLaunchKernelGGL((k_gemm_bf16<X, O, R, BM, BN>), dim3(cnt), dim3(256), 0, s, tl, sg)
+#define DMRG_LB(X, O, R) hipLaunchKernelGGL((k_gemm_bf16<X, O, R, BM, BN, ST>), dim3(cnt), dim3(256), 0, s, tl, sg)
   if (x3) {
     if (out == kOutF64) { if (role == 2) DMRG_LB(true, kOutF64, 2); else DMRG_LB(true, kOutF64, 0); }
     else { if (role == 1) DMRG_LB(true, kOutBf16, 1); else DMRG_LB(true, kOutBf16, 0); }
@@ -339,17 +374,18 @@ void launch_gemm_bf16(const DevGemmB& d, bool x3, int out, int role, hipStream_t
     const unsigned cnt = (unsigned)std::min<size_t>(d.ntiles - off, (size_t)1 << 30);
     const GemmTileB* tl = d.tiles + off;
     switch (d.shape) {
-      case kShape128x128: launch_shape<128, 128>(tl, cnt, d.segs, x3, out, role, s); break;
-      case kShape64x64: launch_shape<64, 64>(tl, cnt, d.segs, x3, out, role, s); break;
-      case kShape64x128: launch_shape<64, 128>(tl, cnt, d.segs, x3, out, role, s); break;
-      default: launch_shape<128, 64>(tl, cnt, d.segs, x3, out, role, s); break;
+      case kShape128x128: launch_shape<128, 128, 2>(tl, cnt, d.segs, x3, out, role, s); break;
+      case kShape128x128s3: launch_shape<128, 128, 3>(tl, cnt, d.segs, x3, out, role, s); break;
+      case kShape64x64: launch_shape<64, 64, 3>(tl, cnt, d.segs, x3, out, role, s); break;
+      case kShape64x128: launch_shape<64, 128, 3>(tl, cnt, d.segs, x3, out, role, s); break;
+      default: launch_shape<128, 64, 3>(tl, cnt, d.segs, x3, out, role, s); break;
     }
   }
   DMRG_HIP(hipGetLastError());
 }
 
 void upload_gemm_bf16(const GemmBatchB& b, DevGemmB& d) {
-  if (b.shape == kShape128x128)  // FP32-only accumulation folds only +-1 scales across segments
+  if (b.shape == kShape128x128 || b.shape == kShape128x128s3)  // FP32 accumulation: +-1 scales only
     for (const GemmTileB& t : b.tiles)
       if (t.seg_end - t.seg_begin > 1)
         for (int k = t.seg_begin; k < t.seg_end; ++k)
