@@ -132,7 +132,8 @@ typedef struct {
   double flops_stage2;   /* left operators x stage-1 results */
   /* BF16 launch configuration per stage, chosen by the autotuner on the
    * first mixed-precision sigma of the window (until then the default):
-   * tile shape (0: 128x64, 1: 64x64, 2: 64x128) + 16 * tile grouping
+   * tile shape (0: 128x64, 1: 64x64, 2: 64x128, 3: 128x128, 4: 128x128 with
+   * three LDS stages, 5: chosen per output problem) + 16 * tile grouping
    * (0: per output problem, 1: per operand-sharing key) + 256 * segment
    * order (1: sorted by operand) */
   int32_t bf_config_stage1, bf_config_stage2;

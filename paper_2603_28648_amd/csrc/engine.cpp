@@ -944,77 +944,106 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
   return plan;
 }
 
+// Tile shape of one output problem in the mixed configuration: the shape
+// with the least padded area per unit of its dense throughput (relative
+// rates of the shapes measured on large GEMMs).
+static int mixed_shape(int m, int n) {
+  static const int cand[4] = {kShape128x128, kShape128x64, kShape64x128, kShape64x64};
+  static const double rate[4] = {1.0, 0.72, 0.72, 0.62};
+  int best = kShape128x128;
+  double bc = 1e300;
+  for (int q = 0; q < 4; ++q) {
+    const int BM = shape_rows(cand[q]), BN = shape_cols(cand[q]);
+    const double c = (double)((m + BM - 1) / BM * BM) * ((n + BN - 1) / BN * BN) / rate[q];
+    if (c < bc) { bc = c; best = cand[q]; }
+  }
+  return best;
+}
+
 // BF16 descriptors of one stage (all chunks) for one launch configuration:
-// tile shape, locality grouping of the tiles (0: each problem its own group,
-// 1: the problems of one key together) and segment order (1: each problem's
-// segments sorted by their A operand).
-static void build_bf_stage(SigmaPlan& plan, int stage, const BfChoice& ch, std::vector<DevGemmB>& out) {
+// tile shape (one for every problem, or kShapeMixed: per problem), locality
+// grouping of the tiles (0: each problem its own group, 1: the problems of
+// one key together) and segment order (1: each problem's segments sorted by
+// their A operand).  out[chunk] holds one launch per tile shape used.
+static void build_bf_stage(SigmaPlan& plan, int stage, const BfChoice& ch,
+                           std::vector<std::vector<DevGemmB>>& out) {
   auto bfp = [&](const BufRef& r) { return plan.bufs[r.buf].bf.as<uint16_t>() + r.off; };
   const std::vector<AStage>& st = stage == 1 ? plan.s1 : plan.s2;
   out.clear();
-  out.reserve(st.size());
-  for (const AStage& A : st) {
-    GemmBatchB b;
-    b.shape = ch.shape;
-    b.segs.reserve(A.segs.size());
+  out.resize(st.size());
+  for (size_t ci = 0; ci < st.size(); ++ci) {
+    const AStage& A = st[ci];
+    std::vector<int> pshape(A.probs.size(), ch.shape);
+    if (ch.shape == kShapeMixed)
+      for (size_t q = 0; q < A.probs.size(); ++q) pshape[q] = mixed_shape(A.probs[q].m, A.probs[q].n);
     std::vector<size_t> order(A.probs.size());
     for (size_t q = 0; q < order.size(); ++q) order[q] = q;
     if (ch.order == 1) order = by_key(A);
-    std::vector<int> keys;
-    std::vector<int64_t> perm;
-    for (size_t q : order) {
-      const AProb& pb = A.probs[q];
-      const size_t s0 = b.segs.size();
-      perm.clear();
-      for (int64_t k = pb.s0; k < pb.s1; ++k) perm.push_back(k);
-      if (ch.sort_a)
-        std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) {
-          return std::tie(A.segs[x].a.buf, A.segs[x].a.off) < std::tie(A.segs[y].a.buf, A.segs[y].a.off);
-        });
-      for (int64_t k : perm) {
-        const ASeg& g = A.segs[k];
-        DMRG_REQUIRE(g.flags == kTransB && g.lda % 8 == 0 && g.ldb % 8 == 0 && g.a.off % 8 == 0 &&
-                         g.b.off % 8 == 0,
-                     kErrState, "prepare_bf16: segment is not an aligned NT product");
-        b.segs.push_back({bfp(g.a), bfp(g.b), plan.bufs[g.a.buf].n, plan.bufs[g.b.buf].n, g.lda,
-                          g.ldb, g.k, g.flags, g.alpha});
+    for (int sh = 0; sh < kNumShapes; ++sh) {
+      GemmBatchB b;
+      b.shape = sh;
+      std::vector<int> keys;
+      std::vector<int64_t> perm;
+      for (size_t q : order) {
+        if (pshape[q] != sh) continue;
+        const AProb& pb = A.probs[q];
+        const size_t s0 = b.segs.size();
+        perm.clear();
+        for (int64_t k = pb.s0; k < pb.s1; ++k) perm.push_back(k);
+        if (ch.sort_a)
+          std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) {
+            return std::tie(A.segs[x].a.buf, A.segs[x].a.off) < std::tie(A.segs[y].a.buf, A.segs[y].a.off);
+          });
+        for (int64_t k : perm) {
+          const ASeg& g = A.segs[k];
+          DMRG_REQUIRE(g.flags == kTransB && g.lda % 8 == 0 && g.ldb % 8 == 0 && g.a.off % 8 == 0 &&
+                           g.b.off % 8 == 0,
+                       kErrState, "prepare_bf16: segment is not an aligned NT product");
+          b.segs.push_back({bfp(g.a), bfp(g.b), plan.bufs[g.a.buf].n, plan.bufs[g.b.buf].n, g.lda,
+                            g.ldb, g.k, g.flags, g.alpha});
+        }
+        if (stage == 1)
+          b.add_problem(bfp(pb.c), plan.bufs[pb.c.buf].n, pb.ldc, pb.m, pb.n, s0, b.segs.size(), 0);
+        else
+          b.add_problem(plan.bufs[pb.c.buf].f64 + pb.c.off, 0, pb.ldc, pb.m, pb.n, s0, b.segs.size(),
+                        pb.beta);
+        keys.resize(b.tiles.size(), ch.order == 1 ? pb.key : (int)q);
       }
-      if (stage == 1)
-        b.add_problem(bfp(pb.c), plan.bufs[pb.c.buf].n, pb.ldc, pb.m, pb.n, s0, b.segs.size(), 0);
-      else
-        b.add_problem(plan.bufs[pb.c.buf].f64 + pb.c.off, 0, pb.ldc, pb.m, pb.n, s0, b.segs.size(),
-                      pb.beta);
-      keys.resize(b.tiles.size(), ch.order == 1 ? pb.key : (int)q);
-    }
-    auto tcost = [&](const GemmTileB& t) {
-      double c = 0;
-      for (int k = t.seg_begin; k < t.seg_end; ++k) c += b.segs[k].k + 32;
-      return c;
-    };
-    if (std::getenv("DMRG_VERBOSE") && std::atoi(std::getenv("DMRG_VERBOSE")) > 1) {
-      double tot = 0, mx = 0;
-      for (auto& t : b.tiles) {
-        const double c = tcost(t);
-        tot += c;
-        mx = std::max(mx, c);
+      if (b.tiles.empty()) continue;
+      auto tcost = [&](const GemmTileB& t) {
+        double c = 0;
+        for (int k = t.seg_begin; k < t.seg_end; ++k) c += b.segs[k].k + 32;
+        return c;
+      };
+      if (std::getenv("DMRG_VERBOSE") && std::atoi(std::getenv("DMRG_VERBOSE")) > 1) {
+        double tot = 0, mx = 0;
+        for (auto& t : b.tiles) {
+          const double c = tcost(t);
+          tot += c;
+          mx = std::max(mx, c);
+        }
+        fprintf(stderr, "[dmrg] stage %d chunk %zu shape %d: %zu tiles, %zu segments, max tile %.3g of total %.3g\n",
+                stage, ci, sh, b.tiles.size(), b.segs.size(), mx, tot);
       }
-      fprintf(stderr, "[dmrg] stage %d chunk %zu: %zu tiles, %zu segments, max tile %.3g of total %.3g (x%.1f of a 512-slot share)\n",
-              stage, out.size(), b.tiles.size(), b.segs.size(), mx, tot, mx / std::max(1.0, tot / 512));
+      xcd_order(b.tiles, keys, tcost);
+      out[ci].emplace_back();
+      upload_gemm_bf16(b, out[ci].back());
     }
-    xcd_order(b.tiles, keys, tcost);
-    out.emplace_back();
-    upload_gemm_bf16(b, out.back());
   }
 }
 
-static void launch_bf_stage(const std::vector<DevGemmB>& d, int stage, bool x3, hipStream_t s) {
+static void launch_bf_chunk(const std::vector<DevGemmB>& d, int stage, bool x3, hipStream_t s) {
   for (const DevGemmB& g : d) launch_gemm_bf16(g, x3, stage == 1 ? kOutBf16 : kOutF64, stage, s);
+}
+static void launch_bf_stage(const std::vector<std::vector<DevGemmB>>& d, int stage, bool x3, hipStream_t s) {
+  for (const auto& c : d) launch_bf_chunk(c, stage, x3, s);
 }
 
 // Event time (ms) of one stage over all chunks, best of reps after a warm-up.
 // The launches write the stage's real outputs (workspace, sigma buffer), which
 // every sigma overwrites or clears first.
-static double time_bf_stage(const std::vector<DevGemmB>& d, int stage, bool x3, hipStream_t s, int reps) {
+static double time_bf_stage(const std::vector<std::vector<DevGemmB>>& d, int stage, bool x3, hipStream_t s,
+                            int reps) {
   hipEvent_t a, b;
   DMRG_HIP(hipEventCreate(&a));
   DMRG_HIP(hipEventCreate(&b));
@@ -1045,14 +1074,14 @@ static void autotune_bf16(SigmaPlan& plan, hipStream_t s) {
   for (int stage = 1; stage <= 2; ++stage) {
     BfChoice best;
     double tbest = 1e300;
-    std::vector<DevGemmB> d;
+    std::vector<std::vector<DevGemmB>> d;
     auto trial = [&](const BfChoice& c) {
       build_bf_stage(plan, stage, c, d);
       const double t = time_bf_stage(d, stage, x3, s, 2);
       plan.tune_log.push_back({stage, c, t});
       if (t < tbest) { tbest = t; best = c; }
     };
-    for (int sh = 0; sh < kNumShapes; ++sh) trial(BfChoice{sh, 0, 0});
+    for (int sh = 0; sh <= kShapeMixed; ++sh) trial(BfChoice{sh, 0, 0});
     const int sh = best.shape;
     trial(BfChoice{sh, 1, 0});
     if (stage == 2) {
@@ -1082,7 +1111,7 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
   const char* env = std::getenv("DMRG_AUTOTUNE");
   if (fixed) {
     const int sh = std::atoi(fixed);
-    DMRG_REQUIRE(sh >= 0 && sh < kNumShapes, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0 to 4");
+    DMRG_REQUIRE(sh >= 0 && sh <= kShapeMixed, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0 to 5");
     plan.bf_choice[0].shape = plan.bf_choice[1].shape = sh;
   } else if (env ? std::atoi(env) != 0 : plan.flops > 5e10) {
     autotune_bf16(plan, s);
@@ -1191,8 +1220,8 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
     launch_split_bf16(T.bf.as<uint16_t>(), T.f64, T.n, s);
     const bool x3 = precision == 2;
     for (size_t c = 0; c < plan.bf_s1.size(); ++c) {
-      timed(1, [&] { launch_gemm_bf16(plan.bf_s1[c], x3, kOutBf16, 1, s); });
-      timed(2, [&] { launch_gemm_bf16(plan.bf_s2[c], x3, kOutF64, 2, s); });
+      timed(1, [&] { launch_bf_chunk(plan.bf_s1[c], 1, x3, s); });
+      timed(2, [&] { launch_bf_chunk(plan.bf_s2[c], 2, x3, s); });
     }
   }
   launch_copy_tasks(plan.unpack_tasks.as<CopyTask>(), plan.n_pack, false, s);

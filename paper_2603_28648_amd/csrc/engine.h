@@ -333,8 +333,9 @@ struct SigmaTiming {
 };
 
 // Launch configuration of the BF16 stages (chosen by the autotuner).
+constexpr int kShapeMixed = kNumShapes;  // tile shape chosen per output problem
 struct BfChoice {
-  int shape = kShape128x64;  // tile shape
+  int shape = kShape128x64;  // tile shape, or kShapeMixed
   int order = 0;             // 0: per-problem XCD groups, 1: groups by locality key
   int sort_a = 0;            // 1: segments of a problem sorted by their A operand
 };
@@ -367,7 +368,7 @@ struct SigmaPlan {
   // materialised descriptors
   std::vector<DevGemm> f64_s1, f64_s2;
   DevGemm f64_p1, f64_p2;
-  std::vector<DevGemmB> bf_s1, bf_s2;
+  std::vector<std::vector<DevGemmB>> bf_s1, bf_s2;  // per chunk: one launch per tile shape
   bool bf_ready = false;
   DevBuf diag;                 // diag(H_eff) for the Davidson preconditioner
   bool diag_ready = false;
