@@ -141,6 +141,15 @@ typedef struct {
 } dmrg_sigma_info;
 dmrg_status dmrg_sigma_get_info(dmrg_ctx ctx, int32_t precision, dmrg_sigma_info* out);
 
+/* Graph replay of the sigma (batching of its launches): with enable = 1,
+ * every sigma of the context (dmrg_sigma and the Davidson solver's) replays
+ * a HIP graph holding all of its launches, captured on the first call per
+ * precision and window; host work (binding the caller's buffers, BF16
+ * preparation) stays outside the graph.  Results are identical to the
+ * launches made one by one.  Default 0; kept across dmrg_build_ops.  Kernel
+ * timing (dmrg_sigma_timing) bypasses the graphs while it is on. */
+dmrg_status dmrg_sigma_graphs(dmrg_ctx ctx, int32_t enable);
+
 /* Kernel timing of dmrg_sigma: HIP events recorded on the context stream
  * around every grouped-GEMM launch of a sigma (diagnostic; off by default).
  * mode 1 resets the totals and starts timing, 0 stops, -1 leaves it as is.

@@ -94,6 +94,7 @@ EXPORTS = {
                                        ctypes.POINTER(ctypes.c_int32)]),
     "dmrg_get_psi": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_sigma_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SigmaTimes)]),
+    "dmrg_sigma_graphs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "dmrg_sigma_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_debug_diag": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -206,6 +207,10 @@ class Context:
         p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self._check(self.lib.dmrg_sigma(self.h, _dev_ptr(psi), _dev_ptr(out), p), self.h)
         return out
+
+    def sigma_graphs(self, enable=True):
+        """Replay every sigma of this context from a captured HIP graph."""
+        self._check(self.lib.dmrg_sigma_graphs(self.h, int(bool(enable))), self.h)
 
     def sigma_timing(self, mode=-1):
         """Kernel timing of sigma calls (mode 1: reset and start, 0: stop,

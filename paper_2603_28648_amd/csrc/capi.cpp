@@ -28,6 +28,7 @@ struct dmrg_ctx_s {
   std::unique_ptr<SigmaPlan> plan;
   DevBuf desc;
   int64_t ws_budget = (int64_t)1 << 30;  // doubles of sigma intermediates (8 GiB)
+  bool use_graphs = false;               // sigma replayed from HIP graphs
   DevBuf next_psi;                       // guess for the window left by dmrg_truncate
   int64_t next_size = -1;
 };
@@ -233,6 +234,7 @@ dmrg_status dmrg_build_ops(dmrg_ctx c, const dmrg_problem* problem, const dmrg_m
       it = (it->first != site + 2 && it->second->bytes() >= kCacheBytes) ? c->right.erase(it) : std::next(it);
     const double t0 = now_s();
     c->plan = plan_sigma(c->P, c->m, *c->left[site], *c->right[site + 2], c->ws_budget, s);
+    c->plan->use_graphs = c->use_graphs;
     DMRG_HIP(hipStreamSynchronize(s));
     if (verbose())
       fprintf(stderr, "[dmrg] sigma plan: %.2f s, %zu pairs, %zu right ops, %.3e flops\n",
@@ -416,6 +418,19 @@ dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* 
   for (auto& kv : c->right) out->operator_bytes += (int64_t)kv.second->bytes();
   if (p.psums) out->operator_bytes += (int64_t)p.psums->bytes();
   return kOk;
+}
+
+dmrg_status dmrg_sigma_graphs(dmrg_ctx c, int32_t enable) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(enable == 0 || enable == 1, kErrInvalidArg, "sigma_graphs: enable must be 0 or 1");
+    c->use_graphs = enable == 1;
+    if (c->plan) {
+      DMRG_HIP(hipStreamSynchronize(c->stream));
+      c->plan->use_graphs = c->use_graphs;
+    }
+    return kOk;
+  });
 }
 
 dmrg_status dmrg_sigma_timing(dmrg_ctx c, int32_t mode, dmrg_sigma_times* out) {

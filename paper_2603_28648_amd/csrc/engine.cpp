@@ -1177,20 +1177,26 @@ SigmaTiming::~SigmaTiming() {
   for (auto e : pool) (void)hipEventDestroy(e);
 }
 
-void plan_load_psi(SigmaPlan& plan, const double* psi, hipStream_t s) {
+static void bind_psi(SigmaPlan& plan, const double* psi, hipStream_t s) {
   if (plan.bound_psi != psi) DMRG_HIP(hipStreamSynchronize(s));
   bind_tasks(plan.pack_host, plan.pack_tasks, psi, nullptr, true, plan.bound_psi);
+}
+static void enqueue_load_psi(SigmaPlan& plan, hipStream_t s) {
   launch_copy_tasks(plan.pack_tasks.as<CopyTask>(), plan.n_pack, false, s);
   launch_copy_tasks(plan.trans_tasks.as<CopyTask>(), plan.n_trans, true, s);
 }
 
-void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision, hipStream_t s) {
+void plan_load_psi(SigmaPlan& plan, const double* psi, hipStream_t s) {
+  bind_psi(plan, psi, s);
+  enqueue_load_psi(plan, s);
+}
+
+// Device work of one sigma (no host synchronisation, so it can be captured).
+static void enqueue_sigma(SigmaPlan& plan, int precision, hipStream_t s) {
   PlanBuf& P = plan.bufs[plan.buf_psi];
   PlanBuf& S = plan.bufs[plan.buf_sig];
   PlanBuf& T = plan.bufs[plan.buf_psit];
-  if (plan.bound_sigma != sigma) DMRG_HIP(hipStreamSynchronize(s));
-  bind_tasks(plan.unpack_host, plan.unpack_tasks, nullptr, sigma, false, plan.bound_sigma);
-  plan_load_psi(plan, psi, s);
+  enqueue_load_psi(plan, s);
   launch_fill(S.f64, 0.0, S.n, s);
   SigmaTiming& tm = plan.timing;
   // runs one launch, bracketed by events when timing is on
@@ -1215,7 +1221,6 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
       timed(2, [&] { launch_gemm_f64(plan.f64_s2[c], s, 2); });
     }
   } else {
-    prepare_bf16(plan, s);
     launch_split_bf16(P.bf.as<uint16_t>(), P.f64, P.n, s);
     launch_split_bf16(T.bf.as<uint16_t>(), T.f64, T.n, s);
     const bool x3 = precision == 2;
@@ -1225,6 +1230,50 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
     }
   }
   launch_copy_tasks(plan.unpack_tasks.as<CopyTask>(), plan.n_pack, false, s);
+}
+
+SigmaGraphs::~SigmaGraphs() {
+  for (auto& e : exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  if (capture) (void)hipStreamDestroy(capture);
+}
+
+void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision, hipStream_t s) {
+  // host-side preparation first: task lists bound to the caller's buffers,
+  // BF16 copies, descriptors and the autotuner (whose trial launches write the
+  // workspace and sigma buffers, both rewritten below)
+  if (plan.bound_sigma != sigma) DMRG_HIP(hipStreamSynchronize(s));
+  bind_tasks(plan.unpack_host, plan.unpack_tasks, nullptr, sigma, false, plan.bound_sigma);
+  bind_psi(plan, psi, s);
+  if (precision != 0) prepare_bf16(plan, s);
+  if (!plan.use_graphs || plan.timing.on) {
+    enqueue_sigma(plan, precision, s);
+    return;
+  }
+  // graph replay: the device work is captured once per precision (on a
+  // stream of the plan's own: the caller's stream may be the null stream,
+  // which cannot be captured) and launched on the caller's stream; the copy
+  // kernels read their task lists from device memory, so the graph serves any
+  // psi / sigma buffers
+  hipGraphExec_t& ex = plan.graphs.exec[precision];
+  if (!ex) {
+    if (!plan.graphs.capture) DMRG_HIP(hipStreamCreateWithFlags(&plan.graphs.capture, hipStreamNonBlocking));
+    hipStream_t cs = plan.graphs.capture;
+    hipGraph_t g = nullptr;
+    DMRG_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      enqueue_sigma(plan, precision, cs);
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    DMRG_HIP(hipStreamEndCapture(cs, &g));
+    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    DMRG_HIP(e);
+  }
+  DMRG_HIP(hipGraphLaunch(ex, s));
 }
 
 }  // namespace dmrg

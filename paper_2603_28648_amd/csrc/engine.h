@@ -345,8 +345,20 @@ struct TuneEntry {
   double ms;
 };
 
+// Executable graphs of the sigma, one per precision (captured on first use).
+struct SigmaGraphs {
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  hipStream_t capture = nullptr;  // stream the graphs are captured on
+  SigmaGraphs() = default;
+  SigmaGraphs(const SigmaGraphs&) = delete;
+  SigmaGraphs& operator=(const SigmaGraphs&) = delete;
+  ~SigmaGraphs();
+};
+
 struct SigmaPlan {
   int window = -1;
+  bool use_graphs = false;  // replay each sigma from a HIP graph
+  SigmaGraphs graphs;
   BfChoice bf_choice[2];            // stage 1, stage 2
   std::vector<TuneEntry> tune_log;  // autotuner trials
   double tune_ms = 0;
