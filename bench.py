@@ -42,6 +42,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(kernel_src, config):
+    """HBM bytes per sigma of the BF16 grouped GEMM from the committed
+    rocprofv3 summary, if it was taken with this kernel source and launch
+    configuration (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_gemm_bf16_sigma_cas54_36_D4096.md")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    m_cfg = re.search(r"bf16_launch_config:\s*(\d+),(\d+)", text)
+    m_tr = re.search(r"traffic_bytes_per_sigma:\s*([0-9.eE+]+)", text)
+    m_ln = re.search(r"launches_per_sigma:\s*(\d+)", text)
+    if not (m_sha and m_cfg and m_tr and m_ln) or m_sha.group(1) != sha:
+        return None
+    if (int(m_cfg.group(1)), int(m_cfg.group(2))) != tuple(config):
+        return None
+    return float(m_tr.group(1)), int(m_ln.group(1))
+
+
 def cpu_baseline(m, n_terms=6, seed=0):
     """Oracle contraction timed on a sample of its partition terms.
 
@@ -89,6 +112,8 @@ def main():
                     help="FP64 sigma steps timed beside the headline precision (0: skip)")
     ap.add_argument("--dav-iters", type=int, default=4,
                     help="Davidson iterations timed with the mixed ladder (0: skip)")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch each sigma kernel by kernel instead of replaying a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-terms", type=int, default=30)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -138,16 +163,18 @@ def main():
     ref = torch.empty_like(psi)
     torch.cuda.synchronize()
 
-    def timed_sigma(prec, steps, warmup, target):
-        """Median event time of `steps` sigma calls on the library stream, and
-        the library's per-launch kernel times over the same calls."""
+    def timed_sigma(prec, steps, warmup, target, kernel_timing):
+        """Event times of `steps` sigma calls on the library stream; with
+        kernel_timing, also the library's per-launch kernel times over the same
+        calls (launched one by one: the timing hook bypasses the graphs)."""
         with torch.cuda.stream(stream):
             for _ in range(warmup):
                 ctx.sigma(psi, target, prec)
         stream.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(steps)]
-        ctx.sigma_timing(1)
+        if kernel_timing:
+            ctx.sigma_timing(1)
         tw = time.perf_counter()
         with torch.cuda.stream(stream):
             for k in range(steps):
@@ -156,7 +183,7 @@ def main():
                 ev[k][1].record(stream)
         stream.synchronize()
         tw = time.perf_counter() - tw
-        kt = ctx.sigma_timing(0)
+        kt = ctx.sigma_timing(0) if kernel_timing else None
         times = np.array([a.elapsed_time(b) for a, b in ev])
         return times, kt, tw
 
@@ -165,12 +192,15 @@ def main():
     with torch.cuda.stream(stream):
         ctx.sigma(psi, ref, "fp64")
     stream.synchronize()
+    ctx.sigma_graphs(not args.no_graphs)
     if args.fp64_steps > 0 and args.precision != "fp64":
-        t64, kt64, _ = timed_sigma("fp64", args.fp64_steps, 0, ref)
+        t64, _, _ = timed_sigma("fp64", args.fp64_steps, 0, ref, False)
         fp64 = {"ms": float(np.median(t64)), "tflops": info["flops"] / (np.median(t64) * 1e-3) / 1e12}
         log(f"[bench] sigma fp64: median {fp64['ms']:.2f} ms ({fp64['tflops']:.2f} TFLOP/s)")
-    times, kt, t_wall = timed_sigma(args.precision, args.steps, args.warmup, out)
+    times, _, t_wall = timed_sigma(args.precision, args.steps, args.warmup, out, False)
     ms = float(np.median(times))
+    # per-kernel times for the roofline: a few more steps with the timing hook
+    _, kt, _ = timed_sigma(args.precision, min(args.steps, 3), 0, out, True)
     info2 = ctx.sigma_info(args.precision)  # after the first mixed sigma: autotuned launch configuration
     tuned = {"stage1": info2["bf_config_stage1"], "stage2": info2["bf_config_stage2"],
              "tune_ms": info2["tune_ms"]}
@@ -221,6 +251,14 @@ def main():
                          f"counted as the library's algorithmic sigma FLOPs"}
         log(f"[bench] cpu oracle: {per:.2f} s/term -> {t_cpu:.0f} s/sigma")
     peak = PEAK_TFLOPS[args.precision]
+    traffic = None
+    if args.precision != "fp64" and args.config == "cas54_36":
+        pt = profiled_traffic(os.path.join(ROOT, "paper_2603_28648_amd", "csrc", "kernels_bf16.hip"),
+                              (tuned["stage1"], tuned["stage2"]))
+        if pt is not None:
+            traffic = pt[0] / pt[1]  # bytes per chunk-stage launch
+    log(f"[bench] HBM traffic per launch from the committed profile: "
+        f"{'%.3e bytes' % traffic if traffic else 'none (kernel or configuration differs)'}")
     res = {
         "metric": METRIC,
         "value": tflops,
@@ -244,9 +282,11 @@ def main():
                    "fp64_sigma_tflops": fp64["tflops"] if fp64 else None,
                    "speedup_vs_fp64": fp64["ms"] / ms if fp64 else None,
                    "bf16_launch_config": tuned if args.precision != "fp64" else None,
+                   "graphs": not args.no_graphs,
                    "davidson": dav},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "kernel": f"{kname} (stage-1 and stage-2 grouped-GEMM launches)",
                      "launches_per_step": n_launch / max(1, kt["calls"]),
                      "avg_launch_ms": ms_kernel,

@@ -1107,9 +1107,25 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
   // DMRG_BF16_SHAPE=0|1|2 fixes the tile shape of both stages (tests of each
   // kernel variant); otherwise DMRG_AUTOTUNE=0|1 switches the autotuner off or
   // on (default: on for plans above 5e10 FLOP per sigma).
+  // DMRG_BF16_CONFIG="c1,c2" fixes the configuration of both stages (codes of
+  // dmrg_sigma_info: shape + 16 * grouping + 256 * segment order), e.g. to
+  // profile the configuration an earlier run chose.
   const char* fixed = std::getenv("DMRG_BF16_SHAPE");
   const char* env = std::getenv("DMRG_AUTOTUNE");
-  if (fixed) {
+  const char* cfg = std::getenv("DMRG_BF16_CONFIG");
+  if (cfg) {
+    int c[2] = {-1, -1};
+    DMRG_REQUIRE(std::sscanf(cfg, "%d,%d", &c[0], &c[1]) == 2, kErrInvalidArg,
+                 "DMRG_BF16_CONFIG must be two codes \"c1,c2\"");
+    for (int k = 0; k < 2; ++k) {
+      BfChoice& b = plan.bf_choice[k];
+      b.shape = c[k] & 15;
+      b.order = (c[k] >> 4) & 15;
+      b.sort_a = (c[k] >> 8) & 1;
+      DMRG_REQUIRE(c[k] >= 0 && b.shape <= kShapeMixed && b.order <= 1, kErrInvalidArg,
+                   "DMRG_BF16_CONFIG: unknown configuration code");
+    }
+  } else if (fixed) {
     const int sh = std::atoi(fixed);
     DMRG_REQUIRE(sh >= 0 && sh <= kShapeMixed, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0 to 5");
     plan.bf_choice[0].shape = plan.bf_choice[1].shape = sh;
