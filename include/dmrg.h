@@ -216,6 +216,18 @@ dmrg_status dmrg_davidson(dmrg_ctx ctx, double* psi_inout, const dmrg_davidson_o
 dmrg_status dmrg_sigma_backward(dmrg_ctx ctx, const double* psi, const double* sigma_bar,
                                 double* dh, double* deri);
 
+/* Orbital gradient for orbital optimisation (DMRG-SCF), the consumer of
+ * dmrg_sigma_backward.  From gamma = dh and Gamma = 2 deri as that call
+ * returns them (device, K*K and K^4) and the context's integrals:
+ *   fock[p][q] = F_pq = sum_r gamma_pr h_qr + sum_rst Gamma_prst (qr|st)
+ *   grad[p][q] = dE/dkappa_pq = 2 (F_qp - F_pq)
+ * the derivative of the energy at a fixed state when the orbitals are
+ * rotated by U = exp(kappa), kappa antisymmetric (h -> U^T h U and likewise
+ * for each index of (pq|rs)); device outputs, K*K each, fock may be NULL.
+ * Synchronises the stream before returning. */
+dmrg_status dmrg_orbital_gradient(dmrg_ctx ctx, const double* dh, const double* deri, double* fock,
+                                  double* grad);
+
 /* Truncates the optimised window psi (device, current window (i, i+1)) and
  * moves the window (two-site DMRG step; the truncation error of the Method
  * section).  The reduced density matrix of the half of the window left

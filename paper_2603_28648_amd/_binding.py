@@ -95,6 +95,8 @@ EXPORTS = {
     "dmrg_get_psi": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_sigma_timing": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SigmaTimes)]),
     "dmrg_sigma_graphs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "dmrg_orbital_gradient": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_sigma_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_debug_diag": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -207,6 +209,16 @@ class Context:
         p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self._check(self.lib.dmrg_sigma(self.h, _dev_ptr(psi), _dev_ptr(out), p), self.h)
         return out
+
+    def orbital_gradient(self, dh, deri):
+        """Generalised Fock matrix and orbital gradient dE/dkappa (K x K each)
+        from the backward's dh, deri and the loaded integrals."""
+        import torch
+        fock = torch.empty_like(dh)
+        grad = torch.empty_like(dh)
+        self._check(self.lib.dmrg_orbital_gradient(self.h, _dev_ptr(dh.contiguous()), _dev_ptr(deri.contiguous()),
+                                                   _dev_ptr(fock), _dev_ptr(grad)), self.h)
+        return fock, grad
 
     def sigma_graphs(self, enable=True):
         """Replay every sigma of this context from a captured HIP graph."""

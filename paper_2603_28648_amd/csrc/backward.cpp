@@ -591,3 +591,35 @@ BackwardStats sigma_backward(const Problem& P0, const Mps& m, int window, const 
 }
 
 }  // namespace dmrg
+
+namespace dmrg {
+
+void orbital_gradient(const Problem& P, const double* dh, const double* deri, double* fock,
+                      double* grad, hipStream_t s) {
+  const int K = P.K;
+  const int64_t K2 = (int64_t)K * K, K3 = K2 * K;
+  DMRG_REQUIRE(K3 < ((int64_t)1 << 31), kErrShape, "orbital_gradient: K^3 exceeds the GEMM index range");
+  std::vector<double> eye((size_t)K2, 0.0);
+  for (int p = 0; p < K; ++p) eye[(size_t)p * K + p] = 1.0;
+  DevBuf dH((size_t)K2 * sizeof(double)), dE((size_t)(K3 * K) * sizeof(double)),
+      dI((size_t)K2 * sizeof(double)), dF((size_t)K2 * sizeof(double)), desc;
+  DMRG_HIP(hipMemcpyAsync(dH.p, P.h.data(), (size_t)K2 * sizeof(double), hipMemcpyHostToDevice, s));
+  DMRG_HIP(hipMemcpyAsync(dE.p, P.eri.data(), (size_t)(K3 * K) * sizeof(double), hipMemcpyHostToDevice, s));
+  DMRG_HIP(hipMemcpyAsync(dI.p, eye.data(), (size_t)K2 * sizeof(double), hipMemcpyHostToDevice, s));
+  double* F = fock ? fock : dF.as<double>();
+  // F = gamma h^T + (2 deri)(K x K^3) eri(K x K^3)^T
+  GemmBatch f;
+  f.segs.push_back({dh, dH.p, K, K, K, kTransB, 1.0});
+  f.segs.push_back({deri, dE.p, (int)K3, (int)K3, (int)K3, kTransB, 2.0});
+  f.add_problem(F, K, K, K, 0, 2, 0);
+  launch_gemm_f64(f, desc, s);
+  // g = 2 F^T I - 2 F I
+  GemmBatch g;
+  g.segs.push_back({F, dI.p, K, K, K, kTransA, 2.0});
+  g.segs.push_back({F, dI.p, K, K, K, 0, -2.0});
+  g.add_problem(grad, K, K, K, 0, 2, 0);
+  launch_gemm_f64(g, desc, s);
+  DMRG_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace dmrg

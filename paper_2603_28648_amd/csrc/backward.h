@@ -18,4 +18,12 @@ struct BackwardStats {
 BackwardStats sigma_backward(const Problem& P, const Mps& m, int window, const double* psi,
                              const double* lam, double* grad, int64_t ws_budget, hipStream_t s);
 
+// Orbital gradient of the energy from the RDMs of sigma_backward: with
+// gamma = dh and Gamma = 2 deri (device, K*K and K^4), the generalised Fock
+// matrix F_pq = sum_r gamma_pr h_qr + sum_rst Gamma_prst (qr|st) and
+// g_pq = dE/dkappa_pq = 2 (F_qp - F_pq) for orbitals rotated by
+// U = exp(kappa) at a fixed state (device outputs, K*K; fock may be null).
+void orbital_gradient(const Problem& P, const double* dh, const double* deri, double* fock,
+                      double* grad, hipStream_t s);
+
 }  // namespace dmrg

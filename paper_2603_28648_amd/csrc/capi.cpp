@@ -286,6 +286,17 @@ dmrg_status dmrg_sigma_backward(dmrg_ctx c, const double* psi, const double* sig
   });
 }
 
+dmrg_status dmrg_orbital_gradient(dmrg_ctx c, const double* dh, const double* deri, double* fock,
+                                  double* grad) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->have_problem, kErrState, "orbital_gradient: no integrals loaded");
+    DMRG_REQUIRE(dh && deri && grad, kErrInvalidArg, "orbital_gradient: NULL buffer");
+    orbital_gradient(c->P, dh, deri, fock, grad, c->stream);
+    return kOk;
+  });
+}
+
 dmrg_status dmrg_davidson(dmrg_ctx c, double* psi, const dmrg_davidson_opts* opts,
                           double* energy_out, dmrg_davidson_stats* stats) {
   if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
