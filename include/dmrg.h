@@ -212,9 +212,13 @@ dmrg_status dmrg_davidson(dmrg_ctx ctx, double* psi_inout, const dmrg_davidson_o
  * sigma_bar = psi normalised these are dE/dh = gamma and dE/d(pq|rs) =
  * Gamma_pqrs / 2 at fixed MPS (every entry an independent input).  The
  * operator adjoints are carried back along both blocks, so the call rebuilds
- * both blocks once (FP64); it synchronises the stream before returning. */
+ * both blocks once (FP64); it synchronises the stream before returning.
+ * precision: DMRG_FP64 runs every adjoint contraction on FP64 MFMA;
+ * DMRG_BF16X3 (the mixed variant) and DMRG_BF16 run them on the BF16 kernel
+ * (split-BF16x3 or plain BF16 products, FP32 accumulation flushed into FP64),
+ * the integral gradient being accumulated in FP64 either way. */
 dmrg_status dmrg_sigma_backward(dmrg_ctx ctx, const double* psi, const double* sigma_bar,
-                                double* dh, double* deri);
+                                double* dh, double* deri, int32_t precision);
 
 /* Orbital gradient for orbital optimisation (DMRG-SCF), the consumer of
  * dmrg_sigma_backward.  From gamma = dh and Gamma = 2 deri as that call

@@ -98,7 +98,7 @@ EXPORTS = {
     "dmrg_orbital_gradient": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_sigma_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                             ctypes.c_void_p, ctypes.c_void_p]),
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "dmrg_debug_diag": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -231,9 +231,10 @@ class Context:
         self._check(self.lib.dmrg_sigma_timing(self.h, int(mode), ctypes.byref(t)), self.h)
         return {k: getattr(t, k) for k, _ in SigmaTimes._fields_}
 
-    def sigma_backward(self, psi, sigma_bar=None, dh=None, deri=None):
+    def sigma_backward(self, psi, sigma_bar=None, dh=None, deri=None, precision="fp64"):
         """Gradient of <sigma_bar, H_eff psi> with respect to h (K x K) and
-        (pq|rs) (K^4): the transition 1-RDM and half the 2-RDM."""
+        (pq|rs) (K^4): the transition 1-RDM and half the 2-RDM.  precision
+        "bf16x3" (or "bf16") runs the adjoint contractions on the BF16 kernel."""
         import torch
         K = self._n_orb
         if dh is None:
@@ -241,7 +242,8 @@ class Context:
         if deri is None:
             deri = torch.empty((K, K, K, K), dtype=torch.float64, device=psi.device)
         lam = ctypes.c_void_p(None) if sigma_bar is None else _dev_ptr(sigma_bar)
-        self._check(self.lib.dmrg_sigma_backward(self.h, _dev_ptr(psi), lam, _dev_ptr(dh), _dev_ptr(deri)),
+        self._check(self.lib.dmrg_sigma_backward(self.h, _dev_ptr(psi), lam, _dev_ptr(dh), _dev_ptr(deri),
+                                                 PRECISIONS[precision] if isinstance(precision, str) else int(precision)),
                     self.h)
         return dh, deri
 

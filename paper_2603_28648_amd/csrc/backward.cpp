@@ -21,7 +21,9 @@
 //      carries the adjoints of block Hamiltonians and complementary
 //      operators to the operators they were built from, and every
 //      coefficient with integral dependence receives <N_bar_t, Proj(x (x) y)>.
-// All contractions are grouped FP64 GEMMs of the same kernel as the forward.
+// All contractions are grouped GEMMs of the forward's kernels: FP64, or the
+// BF16 kernel (BF16 or split-BF16x3 products, FP32 accumulation flushed into
+// FP64) for the mixed variant; the blocks are rebuilt in FP64 either way.
 #include "backward.h"
 
 #include <algorithm>
@@ -196,8 +198,8 @@ void run_adjoint_projections(int side, const Mps& m, int site, const std::vector
       em.xpar = xpar;
       visit(pr, em);
     }
-    launch_gemm_f64(b1, desc, s);
-    launch_gemm_f64(b2, desc, s);
+    launch_gemm(b1, desc, s);
+    launch_gemm(b2, desc, s);
     p = q;
   }
 }
@@ -240,7 +242,7 @@ void gemm(void* c, int ldc, int m, int n, const void* a, int lda, const void* b,
   GemmBatch g;
   g.segs.push_back({a, b, lda, ldb, k, flags, alpha});
   g.add_problem(c, ldc, m, n, 0, 1, beta);
-  launch_gemm_f64(g, desc, s);
+  launch_gemm(g, desc, s);
 }
 
 // One renormalisation step backwards: the adjoints an of the new block's
@@ -434,7 +436,7 @@ void window_back(const Mps& m, const SigmaPlan& plan, const Env& L, const Env& R
       b1.segs.push_back({Z.data + blk->off, Ppad + ps.off_pad[r], blk->ld, ps.ld[r], br.d[r], kTransB, alpha});
       b1.add_problem(ws + t.second, (int)ps.rows_pad[r], br.d[blk->r], (int)ps.rows_pad[r], s0, s0 + 1, 0);
     }
-    launch_gemm_f64(b1, w.desc, s);
+    launch_gemm(b1, w.desc, s);
     // B2 (left adjoints) and B3 (U_bar), output-stationary
     std::map<double*, std::vector<GemmSeg>> outL, outU;
     std::map<double*, std::array<int, 3>> shapeL, shapeU;  // m, n, ldc
@@ -494,7 +496,7 @@ void window_back(const Mps& m, const SigmaPlan& plan, const Env& L, const Env& R
         b2.add_problem(kv.first, sh[2], sh[0], sh[1], s0, b2.segs.size(), 1);
       }
     }
-    launch_gemm_f64(b2, w.desc, s);
+    launch_gemm(b2, w.desc, s);
     // B4: Z_bar[r', r] += a U_bar^T[z, r] psi_r
     GemmBatch b4;
     for (auto& u : uloc) {
@@ -507,7 +509,7 @@ void window_back(const Mps& m, const SigmaPlan& plan, const Env& L, const Env& R
                          (int)ps.rows_pad[r], 0, alpha});
       b4.add_problem(aR.op(R, zr.cls, zr.idx) + blk->off, blk->ld, blk->dr, blk->dc, s0, s0 + 1, 1);
     }
-    launch_gemm_f64(b4, w.desc, s);
+    launch_gemm(b4, w.desc, s);
     DMRG_HIP(hipStreamSynchronize(s));
   }
 }
@@ -515,7 +517,8 @@ void window_back(const Mps& m, const SigmaPlan& plan, const Env& L, const Env& R
 }  // namespace
 
 BackwardStats sigma_backward(const Problem& P0, const Mps& m, int window, const double* psi,
-                             const double* lam, double* grad_out, int64_t ws_budget, hipStream_t s) {
+                             const double* lam, double* grad_out, int64_t ws_budget, hipStream_t s,
+                             int precision) {
   BackwardStats st;
   const int K = P0.K, i = window;
   DMRG_REQUIRE(i >= 0 && i + 1 < K, kErrInvalidArg, "sigma_backward: bad window");
@@ -535,6 +538,9 @@ BackwardStats sigma_backward(const Problem& P0, const Mps& m, int window, const 
   DMRG_HIP(hipStreamSynchronize(s));
   st.ms_chain = now_ms() - t0;
   // ---- window ---------------------------------------------------------------
+  // Every contraction from here on runs in the requested precision; the
+  // gradient itself is accumulated in FP64 on the host.
+  GemmPrecisionScope scope(precision);
   t0 = now_ms();
   const int64_t npad = plan->psi.size_pad;
   DevBuf lam_pad((size_t)std::max<int64_t>(1, npad) * sizeof(double));

@@ -14,9 +14,12 @@ struct BackwardStats {
 // For fixed window vectors psi and lam (API layout of the window) and the
 // fixed MPS, f(h, eri) = <lam, H_eff(h, eri) psi> is linear in the integrals.
 // Writes its gradient to grad (host, K*K entries for h followed by K^4 for
-// eri, same index order as the integrals; overwritten).
+// eri, same index order as the integrals; overwritten).  precision 0: FP64
+// contractions; 1 / 2: BF16 / split-BF16x3 contractions with FP32
+// accumulation flushed into FP64 (the blocks are rebuilt in FP64).
 BackwardStats sigma_backward(const Problem& P, const Mps& m, int window, const double* psi,
-                             const double* lam, double* grad, int64_t ws_budget, hipStream_t s);
+                             const double* lam, double* grad, int64_t ws_budget, hipStream_t s,
+                             int precision = 0);
 
 // Orbital gradient of the energy from the RDMs of sigma_backward: with
 // gamma = dh and Gamma = 2 deri (device, K*K and K^4), the generalised Fock

@@ -264,23 +264,25 @@ dmrg_status dmrg_sigma(dmrg_ctx c, const double* psi, double* sigma, int32_t pre
 }
 
 dmrg_status dmrg_sigma_backward(dmrg_ctx c, const double* psi, const double* sigma_bar, double* dh,
-                                double* deri) {
+                                double* deri, int32_t precision) {
   if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
   return guarded(c, [&]() -> dmrg_status {
     DMRG_REQUIRE(c->plan, kErrState, "sigma_backward: call dmrg_build_ops first");
     DMRG_REQUIRE(psi && dh && deri, kErrInvalidArg, "sigma_backward: NULL buffer");
+    DMRG_REQUIRE(precision == DMRG_FP64 || precision == DMRG_BF16 || precision == DMRG_BF16X3,
+                 kErrInvalidArg, "sigma_backward: unknown precision");
     const int K = c->P.K;
     const size_t n1 = (size_t)K * K, n2 = n1 * n1;
     std::vector<double> g(n1 + n2);
     const double t0 = now_s();
     BackwardStats st = sigma_backward(c->P, c->m, c->window, psi, sigma_bar ? sigma_bar : psi, g.data(),
-                                      c->ws_budget, c->stream);
+                                      c->ws_budget, c->stream, precision);
     DMRG_HIP(hipMemcpyAsync(dh, g.data(), n1 * sizeof(double), hipMemcpyHostToDevice, c->stream));
     DMRG_HIP(hipMemcpyAsync(deri, g.data() + n1, n2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
     DMRG_HIP(hipStreamSynchronize(c->stream));
     if (verbose())
-      fprintf(stderr, "[dmrg] backward window %d: rebuild %.1f ms, window %.1f ms, chains %.1f ms, %lld groups (%.1f ms)\n",
-              c->window, st.ms_chain, st.ms_window, st.ms_adjoint, (long long)st.n_groups,
+      fprintf(stderr, "[dmrg] backward window %d (precision %d): rebuild %.1f ms, window %.1f ms, chains %.1f ms, %lld groups (%.1f ms)\n",
+              c->window, precision, st.ms_chain, st.ms_window, st.ms_adjoint, (long long)st.n_groups,
               1e3 * (now_s() - t0));
     return kOk;
   });

@@ -205,8 +205,8 @@ void run_projections(int side, const Mps& m, int site, const std::vector<Project
         b2.add_problem(pr.dst + tb.off, tb.ld, tb.dr, tb.dc, s0, s1, 1);
       }
     }
-    launch_gemm_f64(b1, desc, s);
-    launch_gemm_f64(b2, desc, s);
+    launch_gemm(b1, desc, s);
+    launch_gemm(b2, desc, s);
     p = q;
   }
 }

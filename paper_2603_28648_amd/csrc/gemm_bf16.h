@@ -66,8 +66,38 @@ struct DevGemmB {
   int shape = kShape128x64;
 };
 
+// One operand of a repacking pass: the rows x k matrix X (element (i, kk) at
+// src[kk * ld + i] if colmajor, else src[i * ld + kk]) written as BF16 hi
+// (at base + dst) and lo (at base + dst + rows * kp) planes, rows of kp
+// (k rounded up to 8, zero-padded) elements.  chunk0: the first of its
+// rows * kp / 8 16-byte chunks in the pass.
+struct PackOp {
+  const double* src;
+  int64_t dst, chunk0;
+  int32_t ld, rows, k, kp, colmajor, pad;
+};
+void launch_pack_bf16(const PackOp* ops, int nops, int64_t chunks, uint16_t* base, hipStream_t s);
+
 void upload_gemm_bf16(const GemmBatchB& b, DevGemmB& d);
 void launch_gemm_bf16(const DevGemmB& d, bool x3, int out, int role, hipStream_t s);
 void launch_split_bf16(uint16_t* out, const double* x, int64_t n, hipStream_t s);
+
+// ---- FP64 task lists executed on the BF16 kernel -----------------------------
+// launch_gemm runs a GemmBatch of FP64 operands (any storage order) with the
+// FP64 kernel, or, inside a GemmPrecisionScope for BF16 / split-BF16x3, with
+// the BF16 kernel: every distinct operand is repacked once per launch into
+// k-contiguous hi/lo planes, products accumulate in FP32, are flushed into an
+// FP64 register accumulator every few segments and added to the FP64 output
+// (64 x 64 tiles; segment scales applied in FP64 at the flush).
+struct GemmPrecisionScope {
+  explicit GemmPrecisionScope(int precision);  // 0 FP64, 1 BF16, 2 split-BF16x3
+  ~GemmPrecisionScope();
+  GemmPrecisionScope(const GemmPrecisionScope&) = delete;
+  GemmPrecisionScope& operator=(const GemmPrecisionScope&) = delete;
+  int precision, prev;
+  DevBuf pack, ops, desc;
+  double ms_pack = 0;  // host time of the repacking passes
+};
+void launch_gemm(const GemmBatch& b, DevBuf& desc, hipStream_t s);
 
 }  // namespace dmrg
