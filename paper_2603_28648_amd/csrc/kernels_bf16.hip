@@ -427,45 +427,4 @@ void launch_split_bf16(uint16_t* out, const double* x, int64_t n, hipStream_t s)
   DMRG_HIP(hipGetLastError());
 }
 
-// FP64 operands (either storage order) -> k-contiguous BF16 hi/lo planes,
-// one 16-byte chunk of eight k entries per thread.
-__global__ void k_pack_bf16(const PackOp* __restrict__ ops, int nops, int64_t chunks, uint16_t* base) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < chunks;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int lo = 0, hi = nops - 1;  // last op with chunk0 <= g
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (ops[mid].chunk0 <= g) lo = mid; else hi = mid - 1;
-    }
-    const PackOp op = ops[lo];
-    const int64_t c = g - op.chunk0;
-    const int per_row = op.kp >> 3;
-    const int i = (int)(c / per_row), k0 = 8 * (int)(c % per_row);
-    uint16_t h[8], l[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int kk = k0 + e;
-      double x = 0.0;
-      if (kk < op.k) x = op.colmajor ? op.src[(int64_t)kk * op.ld + i] : op.src[(int64_t)i * op.ld + kk];
-      h[e] = f32_to_bf16_rn((float)x);
-      l[e] = f32_to_bf16_rn((float)(x - (double)bf16_to_f32(h[e])));
-    }
-    uint16_t* dh = base + op.dst + (int64_t)i * op.kp + k0;
-    uint16_t* dl = dh + (int64_t)op.rows * op.kp;
-    V8s vh, vl;
-    vh.x = h[0] | ((uint32_t)h[1] << 16); vh.y = h[2] | ((uint32_t)h[3] << 16);
-    vh.z = h[4] | ((uint32_t)h[5] << 16); vh.w = h[6] | ((uint32_t)h[7] << 16);
-    vl.x = l[0] | ((uint32_t)l[1] << 16); vl.y = l[2] | ((uint32_t)l[3] << 16);
-    vl.z = l[4] | ((uint32_t)l[5] << 16); vl.w = l[6] | ((uint32_t)l[7] << 16);
-    *reinterpret_cast<V8s*>(dh) = vh;
-    *reinterpret_cast<V8s*>(dl) = vl;
-  }
-}
-void launch_pack_bf16(const PackOp* ops, int nops, int64_t chunks, uint16_t* base, hipStream_t s) {
-  if (chunks <= 0 || nops <= 0) return;
-  const int64_t g = std::max<int64_t>(1, std::min<int64_t>((chunks + 255) / 256, 16384));
-  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)g), dim3(256), 0, s, ops, nops, chunks, base);
-  DMRG_HIP(hipGetLastError());
-}
-
 }  // namespace dmrg
