@@ -68,6 +68,11 @@ typedef int32_t dmrg_status;
 #define DMRG_FP64 0   /* FP64 MFMA, FP64 accumulation */
 #define DMRG_BF16 1   /* BF16 MFMA, FP32 accumulation, FP64 output */
 #define DMRG_BF16X3 2 /* split-BF16 (hi*hi + hi*lo + lo*hi), FP32 accumulation */
+#define DMRG_OZAKI 3  /* FP64 emulated on INT8 MFMA (Ozaki scheme; Hardware section):
+                         each operand row scaled by a power of two and split into
+                         kappa signed 8-bit digits (8 kappa - 1 bits, kappa from
+                         DMRG_OZAKI_SLICES, default 6: 47 bits), the kappa (kappa+1)/2
+                         leading digit products exact in INT32, combined in FP64 */
 
 typedef struct dmrg_ctx_s* dmrg_ctx;
 
@@ -162,6 +167,10 @@ typedef struct {
   int32_t launches_pinned;    /* FP64 launches of the block-Hamiltonian pairs */
   double ms_stage1, ms_stage2, ms_pinned;
   double flops_stage1, flops_stage2, flops_pinned;  /* algorithmic FLOPs of one call */
+  int32_t launches_convert;   /* operand conversion launches (DMRG_OZAKI: digit slicing of psi and of
+                                 the stage-1 results) */
+  int32_t pad;
+  double ms_convert;
 } dmrg_sigma_times;
 dmrg_status dmrg_sigma_timing(dmrg_ctx ctx, int32_t mode, dmrg_sigma_times* out);
 
@@ -190,7 +199,7 @@ typedef struct {
 typedef struct {
   double energy, residual, time_ms, sigma_ms;
   int32_t iterations, converged;
-  int32_t n_sigma[3];    /* sigma products per precision */
+  int32_t n_sigma[4];    /* sigma products per precision (DMRG_FP64 .. DMRG_OZAKI) */
   int32_t n_history;     /* entries used below (<= 256) */
   double residual_history[256];
   int32_t stage_history[256];

@@ -13,8 +13,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmrg_mi355x.so")
 
-DMRG_FP64, DMRG_BF16, DMRG_BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": DMRG_FP64, "bf16": DMRG_BF16, "bf16x3": DMRG_BF16X3}
+DMRG_FP64, DMRG_BF16, DMRG_BF16X3, DMRG_OZAKI = 0, 1, 2, 3
+PRECISIONS = {"fp64": DMRG_FP64, "bf16": DMRG_BF16, "bf16x3": DMRG_BF16X3, "ozaki": DMRG_OZAKI}
 
 STATUS = {0: "OK", 1: "WARN_NOT_CONVERGED", -1: "INVALID_ARG", -2: "SHAPE", -3: "HIP",
           -4: "OOM", -5: "NO_DEVICE", -6: "UNIMPLEMENTED", -7: "STATE"}
@@ -66,14 +66,15 @@ class SigmaTimes(ctypes.Structure):
                 ("launches_stage2", ctypes.c_int32), ("launches_pinned", ctypes.c_int32),
                 ("ms_stage1", ctypes.c_double), ("ms_stage2", ctypes.c_double),
                 ("ms_pinned", ctypes.c_double), ("flops_stage1", ctypes.c_double),
-                ("flops_stage2", ctypes.c_double), ("flops_pinned", ctypes.c_double)]
+                ("flops_stage2", ctypes.c_double), ("flops_pinned", ctypes.c_double),
+                ("launches_convert", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms_convert", ctypes.c_double)]
 
 
 class DavidsonStats(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("residual", ctypes.c_double),
                 ("time_ms", ctypes.c_double), ("sigma_ms", ctypes.c_double),
                 ("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("n_sigma", ctypes.c_int32 * 3), ("n_history", ctypes.c_int32),
+                ("n_sigma", ctypes.c_int32 * 4), ("n_history", ctypes.c_int32),
                 ("residual_history", ctypes.c_double * 256),
                 ("stage_history", ctypes.c_int32 * 256)]
 
@@ -270,7 +271,8 @@ class Context:
         return {"energy": e.value, "residual": st.residual, "time_ms": st.time_ms,
                 "sigma_ms": st.sigma_ms, "iterations": st.iterations,
                 "converged": bool(st.converged), "status": status,
-                "n_sigma": {"fp64": st.n_sigma[0], "bf16": st.n_sigma[1], "bf16x3": st.n_sigma[2]},
+                "n_sigma": {"fp64": st.n_sigma[0], "bf16": st.n_sigma[1], "bf16x3": st.n_sigma[2],
+                            "ozaki": st.n_sigma[3]},
                 "residual_history": list(st.residual_history[:n]),
                 "stage_history": list(st.stage_history[:n])}
 

@@ -257,7 +257,7 @@ dmrg_status dmrg_sigma(dmrg_ctx c, const double* psi, double* sigma, int32_t pre
   return guarded(c, [&]() -> dmrg_status {
     DMRG_REQUIRE(c->plan, kErrState, "sigma: call dmrg_build_ops first");
     DMRG_REQUIRE(psi && sigma, kErrInvalidArg, "sigma: NULL buffer");
-    DMRG_REQUIRE(precision >= 0 && precision <= 2, kErrInvalidArg, "sigma: unknown precision");
+    DMRG_REQUIRE(precision >= 0 && precision <= 3, kErrInvalidArg, "sigma: unknown precision");
     run_sigma(*c->plan, psi, sigma, precision, c->stream);
     return kOk;
   });
@@ -317,7 +317,7 @@ dmrg_status dmrg_davidson(dmrg_ctx c, double* psi, const dmrg_davidson_opts* opt
     DMRG_REQUIRE(o.tol > 0, kErrInvalidArg, "davidson: tol must be positive");
     DMRG_REQUIRE(o.n_ladder >= 1 && o.n_ladder <= 4, kErrInvalidArg, "davidson: 1 <= n_ladder <= 4");
     for (int k = 0; k < o.n_ladder; ++k) {
-      DMRG_REQUIRE(opts->ladder[k] >= 0 && opts->ladder[k] <= 2, kErrInvalidArg, "davidson: bad ladder precision");
+      DMRG_REQUIRE(opts->ladder[k] >= 0 && opts->ladder[k] <= 3, kErrInvalidArg, "davidson: bad ladder precision");
       o.ladder[k] = opts->ladder[k];
       o.ladder_tol[k] = opts->ladder_tol[k];
     }
@@ -338,7 +338,7 @@ dmrg_status dmrg_davidson(dmrg_ctx c, double* psi, const dmrg_davidson_opts* opt
       stats->sigma_ms = r.sigma_ms;
       stats->iterations = r.iterations;
       stats->converged = r.converged;
-      for (int k = 0; k < 3; ++k) stats->n_sigma[k] = r.n_sigma[k];
+      for (int k = 0; k < 4; ++k) stats->n_sigma[k] = r.n_sigma[k];
       const int nh = (int)std::min<size_t>(256, r.residual_history.size());
       stats->n_history = nh;
       for (int k = 0; k < nh; ++k) {
@@ -413,7 +413,10 @@ dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* 
   out->flops = p.flops;
   out->flops_stage1 = p.flops_stage1;
   out->flops_stage2 = p.flops_stage2;
-  out->hw_flops = precision == DMRG_BF16X3 ? 3 * p.flops : p.flops;
+  const int kap = precision == DMRG_OZAKI ? ozaki_kappa() : 0;
+  out->hw_flops = precision == DMRG_BF16X3 ? 3 * p.flops
+                  : precision == DMRG_OZAKI ? 0.5 * kap * (kap + 1) * p.flops
+                                            : p.flops;
   out->n_pairs = (int64_t)p.pairs.size();
   out->n_right_ops = (int64_t)p.zops.size();
   for (auto& g : p.f64_s1) out->n_stage1_tiles += (int64_t)g.ntiles;
@@ -465,6 +468,8 @@ dmrg_status dmrg_sigma_timing(dmrg_ctx c, int32_t mode, dmrg_sigma_times* out) {
       out->ms_stage1 = t.ms[1];
       out->ms_stage2 = t.ms[2];
       out->ms_pinned = t.ms[3];
+      out->launches_convert = t.launches[0];
+      out->ms_convert = t.ms[0];
       for (auto& a : p.s1) out->flops_stage1 += a.flops;
       for (auto& a : p.s2) out->flops_stage2 += a.flops;
       out->flops_pinned = p.p1.flops + p.p2.flops;
@@ -484,13 +489,42 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const d
     DMRG_REQUIRE(beta == 0 || beta == 1, kErrInvalidArg, "debug_gemm: beta must be 0 or 1");
     DMRG_REQUIRE(lda >= (trans_a ? m : k) && ldb >= (trans_b ? k : n) && ldc >= n, kErrInvalidArg,
                  "debug_gemm: leading dimension too small");
-    DMRG_REQUIRE(precision >= 0 && precision <= 2, kErrInvalidArg, "debug_gemm: unknown precision");
+    DMRG_REQUIRE(precision >= 0 && precision <= 3, kErrInvalidArg, "debug_gemm: unknown precision");
     const int flags = (trans_a ? kTransA : 0) | (trans_b ? kTransB : 0);
     if (precision == DMRG_FP64) {
       GemmBatch bt;
       bt.segs.push_back({a, b, lda, ldb, k, flags, alpha});
       bt.add_problem(cc, ldc, m, n, 0, 1, beta);
       launch_gemm_f64(bt, c->desc, c->stream);
+      return kOk;
+    }
+    if (precision == DMRG_OZAKI) {
+      // digit planes of A (m rows) and of B's n x k storage (n rows)
+      const int kappa = ozaki_kappa(), kp = oz_kp(k);
+      const int64_t pa = (int64_t)m * kp, pb = (int64_t)n * kp;
+      SliceOp ops[2] = {};
+      ops[0] = {a, 0, pa, 0, 0, lda, m, k, kp, trans_a ? 1 : 0, 0};
+      ops[1] = {b, kappa * pa, pb, m, m, ldb, n, k, kp, trans_b ? 0 : 1, 0};
+      DevBuf arena((size_t)(kappa * (pa + pb))), exps((size_t)(m + n) * sizeof(int32_t)), dops(sizeof(ops));
+      DMRG_HIP(hipMemcpyAsync(dops.p, ops, sizeof(ops), hipMemcpyHostToDevice, c->stream));
+      launch_slice_oz(dops.as<SliceOp>(), 2, m + n, arena.as<int8_t>(), exps.as<int32_t>(), kappa, c->stream);
+      GemmBatchO bt;
+      GemmSegO g{};
+      g.a = arena.as<int8_t>();
+      g.b = arena.as<int8_t>() + kappa * pa;
+      g.ea = exps.as<int32_t>();
+      g.eb = exps.as<int32_t>() + m;
+      g.a_plane = pa;
+      g.b_plane = pb;
+      g.lda = g.ldb = kp;
+      g.k = k;
+      g.alpha = alpha;
+      bt.segs.push_back(g);
+      bt.add_problem(cc, ldc, m, n, 0, 1, beta);
+      DevGemmO d;
+      upload_gemm_oz(bt, kappa, d);
+      launch_gemm_oz(d, kappa, c->stream);
+      DMRG_HIP(hipStreamSynchronize(c->stream));
       return kOk;
     }
     // padded NT copies: A as m x pad8(k) rows, B as n x pad8(k) rows, then BF16 hi/lo

@@ -27,7 +27,7 @@ struct DavidsonResult {
   double energy = 0, residual = 0, time_ms = 0, sigma_ms = 0;
   int iterations = 0;
   bool converged = false;
-  int n_sigma[3] = {0, 0, 0};
+  int n_sigma[4] = {0, 0, 0, 0};
   std::vector<double> residual_history;
   std::vector<int> stage_history;
 };

@@ -1032,6 +1032,170 @@ static void build_bf_stage(SigmaPlan& plan, int stage, const BfChoice& ch,
   }
 }
 
+int ozaki_kappa() {
+  int k = 6;
+  if (const char* e = std::getenv("DMRG_OZAKI_SLICES")) k = std::atoi(e);
+  DMRG_REQUIRE(k >= kOzMinKappa && k <= kOzMaxKappa, kErrInvalidArg,
+               "DMRG_OZAKI_SLICES must lie in [3, 7]");
+  return k;
+}
+
+void prepare_ozaki(SigmaPlan& plan, hipStream_t s) {
+  const int kappa = ozaki_kappa();
+  if (plan.oz.kappa == kappa) return;
+  DMRG_HIP(hipStreamSynchronize(s));
+  plan.oz = OzPlan();
+  OzPlan& oz = plan.oz;
+  // distinct operands: (buffer, offset, ld, k, chunk of a workspace operand)
+  struct Opnd {
+    int cls;  // 0 static, 1 psi, 2 workspace
+    int chunk;
+    const double* src;
+    int ld, k, rows;
+    int64_t dst = 0, exp = 0;
+  };
+  std::vector<Opnd> ops;
+  std::map<std::tuple<int, int64_t, int, int, int>, int> index;
+  auto cls_of = [&](int buf) {
+    if (buf == plan.buf_psi || buf == plan.buf_psit) return 1;
+    if (buf == plan.buf_ws) return 2;
+    return 0;
+  };
+  auto operand = [&](const BufRef& r, int ld, int k, int rows, int chunk) {
+    const int cls = cls_of(r.buf);
+    const int ch = cls == 2 ? chunk : -1;
+    auto key = std::make_tuple(r.buf, r.off, ld, k, ch);
+    auto it = index.find(key);
+    if (it == index.end()) {
+      it = index.emplace(key, (int)ops.size()).first;
+      ops.push_back({cls, ch, plan.bufs[r.buf].f64 + r.off, ld, k, 0});
+    }
+    ops[it->second].rows = std::max(ops[it->second].rows, rows);
+    return it->second;
+  };
+  const size_t nch = plan.s1.size();
+  // per stage and chunk: the operands of each segment
+  std::vector<std::vector<std::pair<int, int>>> segops[2];
+  for (int st = 0; st < 2; ++st) {
+    const std::vector<AStage>& S = st == 0 ? plan.s1 : plan.s2;
+    segops[st].resize(nch);
+    for (size_t c = 0; c < nch; ++c) {
+      const AStage& A = S[c];
+      segops[st][c].assign(A.segs.size(), {-1, -1});
+      for (const AProb& pb : A.probs)
+        for (int64_t q = pb.s0; q < pb.s1; ++q) {
+          const ASeg& g = A.segs[(size_t)q];
+          DMRG_REQUIRE(g.flags == kTransB, kErrState, "prepare_ozaki: segment is not an NT product");
+          segops[st][c][(size_t)q] = {operand(g.a, g.lda, g.k, pb.m, (int)c), operand(g.b, g.ldb, g.k, pb.n, (int)c)};
+        }
+    }
+  }
+  // layout: static operands, psi operands, then one workspace region reused
+  // by every chunk
+  int64_t bytes = 0, rows = 0;
+  auto place = [&](Opnd& o) {
+    o.dst = bytes;
+    o.exp = rows;
+    bytes += (int64_t)kappa * o.rows * oz_kp(o.k);
+    rows += o.rows;
+  };
+  for (Opnd& o : ops)
+    if (o.cls == 0) place(o);
+  oz.rows_static = rows;
+  const int64_t psi_row0 = rows;
+  for (Opnd& o : ops)
+    if (o.cls == 1) place(o);
+  oz.rows_psi = rows - psi_row0;
+  const int64_t ws_bytes0 = bytes, ws_rows0 = rows;
+  int64_t ws_bytes_max = 0, ws_rows_max = 0;
+  oz.rows_ws.assign(nch, 0);
+  for (size_t c = 0; c < nch; ++c) {
+    bytes = ws_bytes0;
+    rows = ws_rows0;
+    for (Opnd& o : ops)
+      if (o.cls == 2 && o.chunk == (int)c) place(o);
+    ws_bytes_max = std::max(ws_bytes_max, bytes - ws_bytes0);
+    ws_rows_max = std::max(ws_rows_max, rows - ws_rows0);
+    oz.rows_ws[c] = rows - ws_rows0;
+  }
+  oz.arena_bytes = ws_bytes0 + ws_bytes_max;
+  oz.arena.alloc((size_t)std::max<int64_t>(oz.arena_bytes, 256));
+  oz.exps.alloc((size_t)std::max<int64_t>(ws_rows0 + ws_rows_max, 1) * sizeof(int32_t));
+  int8_t* arena = oz.arena.as<int8_t>();
+  int32_t* exps = oz.exps.as<int32_t>();
+  // slicing passes
+  auto slice_list = [&](int cls, int chunk, DevBuf& out, int& n) {
+    std::vector<SliceOp> v;
+    int64_t r0 = 0;
+    for (const Opnd& o : ops) {
+      if (o.cls != cls || (cls == 2 && o.chunk != chunk)) continue;
+      SliceOp so{};
+      so.src = o.src;
+      so.dst = o.dst;
+      so.plane = (int64_t)o.rows * oz_kp(o.k);
+      so.exp = o.exp;
+      so.row0 = r0;
+      so.ld = o.ld;
+      so.rows = o.rows;
+      so.k = o.k;
+      so.kp = oz_kp(o.k);
+      so.colmajor = 0;
+      r0 += o.rows;
+      v.push_back(so);
+    }
+    n = (int)v.size();
+    out.alloc(std::max<size_t>(1, v.size()) * sizeof(SliceOp));
+    if (!v.empty()) DMRG_HIP(hipMemcpy(out.p, v.data(), v.size() * sizeof(SliceOp), hipMemcpyHostToDevice));
+  };
+  slice_list(0, -1, oz.ops_static, oz.n_static);
+  slice_list(1, -1, oz.ops_psi, oz.n_psi);
+  oz.ops_ws.resize(nch);
+  oz.n_ws.assign(nch, 0);
+  for (size_t c = 0; c < nch; ++c) slice_list(2, (int)c, oz.ops_ws[c], oz.n_ws[c]);
+  // task lists
+  oz.s1.resize(nch);
+  oz.s2.resize(nch);
+  for (int st = 0; st < 2; ++st)
+    for (size_t c = 0; c < nch; ++c) {
+      const AStage& A = (st == 0 ? plan.s1 : plan.s2)[c];
+      GemmBatchO b;
+      std::vector<int> keys;
+      for (size_t q : by_key(A)) {
+        const AProb& pb = A.probs[q];
+        const size_t s0 = b.segs.size();
+        for (int64_t k = pb.s0; k < pb.s1; ++k) {
+          const ASeg& g = A.segs[(size_t)k];
+          const Opnd& oa = ops[(size_t)segops[st][c][(size_t)k].first];
+          const Opnd& ob = ops[(size_t)segops[st][c][(size_t)k].second];
+          GemmSegO so{};
+          so.a = arena + oa.dst;
+          so.b = arena + ob.dst;
+          so.ea = exps + oa.exp;
+          so.eb = exps + ob.exp;
+          so.a_plane = (int64_t)oa.rows * oz_kp(oa.k);
+          so.b_plane = (int64_t)ob.rows * oz_kp(ob.k);
+          so.lda = oz_kp(oa.k);
+          so.ldb = oz_kp(ob.k);
+          so.k = g.k;
+          so.alpha = g.alpha;
+          b.segs.push_back(so);
+        }
+        b.add_problem(plan.bufs[pb.c.buf].f64 + pb.c.off, pb.ldc, pb.m, pb.n, s0, b.segs.size(), pb.beta);
+        keys.resize(b.tiles.size(), pb.key);
+      }
+      xcd_order(b.tiles, keys, [&](const GemmTileB& t) {
+        double cst = 0;
+        for (int k = t.seg_begin; k < t.seg_end; ++k) cst += b.segs[k].k + 64;
+        return cst;
+      });
+      upload_gemm_oz(b, kappa, st == 0 ? oz.s1[c] : oz.s2[c]);
+    }
+  oz.kappa = kappa;
+  if (std::getenv("DMRG_VERBOSE"))
+    fprintf(stderr, "[dmrg] Ozaki plan: %d slices, %zu operands, %.2f GB of digit planes\n", kappa, ops.size(),
+            oz.arena_bytes / 1e9);
+}
+
 static void launch_bf_chunk(const std::vector<DevGemmB>& d, int stage, bool x3, hipStream_t s) {
   for (const DevGemmB& g : d) launch_gemm_bf16(g, x3, stage == 1 ? kOutBf16 : kOutF64, stage, s);
 }
@@ -1236,6 +1400,26 @@ static void enqueue_sigma(SigmaPlan& plan, int precision, hipStream_t s) {
       timed(1, [&] { launch_gemm_f64(plan.f64_s1[c], s, 1); });
       timed(2, [&] { launch_gemm_f64(plan.f64_s2[c], s, 2); });
     }
+  } else if (precision == 3) {
+    OzPlan& oz = plan.oz;
+    const int kappa = oz.kappa;
+    if (!oz.statics_sliced) {
+      launch_slice_oz(oz.ops_static.as<SliceOp>(), oz.n_static, oz.rows_static, oz.arena.as<int8_t>(),
+                      oz.exps.as<int32_t>(), kappa, s);
+      oz.statics_sliced = true;
+    }
+    timed(0, [&] {
+      launch_slice_oz(oz.ops_psi.as<SliceOp>(), oz.n_psi, oz.rows_psi, oz.arena.as<int8_t>(),
+                      oz.exps.as<int32_t>(), kappa, s);
+    });
+    for (size_t c = 0; c < oz.s1.size(); ++c) {
+      timed(1, [&] { launch_gemm_oz(oz.s1[c], kappa, s); });
+      timed(0, [&] {
+        launch_slice_oz(oz.ops_ws[c].as<SliceOp>(), oz.n_ws[c], oz.rows_ws[c], oz.arena.as<int8_t>(),
+                        oz.exps.as<int32_t>(), kappa, s);
+      });
+      timed(2, [&] { launch_gemm_oz(oz.s2[c], kappa, s); });
+    }
   } else {
     launch_split_bf16(P.bf.as<uint16_t>(), P.f64, P.n, s);
     launch_split_bf16(T.bf.as<uint16_t>(), T.f64, T.n, s);
@@ -1261,8 +1445,9 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
   if (plan.bound_sigma != sigma) DMRG_HIP(hipStreamSynchronize(s));
   bind_tasks(plan.unpack_host, plan.unpack_tasks, nullptr, sigma, false, plan.bound_sigma);
   bind_psi(plan, psi, s);
-  if (precision != 0) prepare_bf16(plan, s);
-  if (!plan.use_graphs || plan.timing.on) {
+  if (precision == 1 || precision == 2) prepare_bf16(plan, s);
+  if (precision == 3) prepare_ozaki(plan, s);
+  if (!plan.use_graphs || plan.timing.on || precision == 3) {
     enqueue_sigma(plan, precision, s);
     return;
   }

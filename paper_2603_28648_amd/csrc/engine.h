@@ -9,6 +9,7 @@
 #include "common.h"
 #include "gemm.h"
 #include "gemm_bf16.h"
+#include "gemm_oz.h"
 #include "strings.h"
 
 namespace dmrg {
@@ -355,6 +356,24 @@ struct SigmaGraphs {
   ~SigmaGraphs();
 };
 
+// Ozaki-scheme sigma (precision 3): digit planes and row exponents of every
+// distinct operand of the two stages in one arena: operators and window
+// partial sums (sliced once per plan), psi (sliced per sigma) and the
+// stage-1 workspace (sliced per chunk, a region shared by the chunks).
+struct OzPlan {
+  int kappa = 0;  // 0: not prepared
+  DevBuf arena, exps;
+  DevBuf ops_static, ops_psi;
+  int n_static = 0, n_psi = 0;
+  int64_t rows_static = 0, rows_psi = 0;
+  std::vector<DevBuf> ops_ws;  // per chunk
+  std::vector<int> n_ws;
+  std::vector<int64_t> rows_ws;
+  std::vector<DevGemmO> s1, s2;  // per chunk
+  bool statics_sliced = false;
+  int64_t arena_bytes = 0;
+};
+
 struct SigmaPlan {
   int window = -1;
   bool use_graphs = false;  // replay each sigma from a HIP graph
@@ -382,6 +401,7 @@ struct SigmaPlan {
   DevGemm f64_p1, f64_p2;
   std::vector<std::vector<DevGemmB>> bf_s1, bf_s2;  // per chunk: one launch per tile shape
   bool bf_ready = false;
+  OzPlan oz;
   DevBuf diag;                 // diag(H_eff) for the Davidson preconditioner
   bool diag_ready = false;
   double flops = 0;            // algorithmic FLOPs of one sigma
@@ -405,8 +425,13 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
 // Copies psi (API layout) into the plan's padded psi buffer and its transpose.
 void plan_load_psi(SigmaPlan& plan, const double* psi, hipStream_t s);
 // sigma = H_eff psi (device pointers, right-sector-major psi layout).
-// precision: 0 FP64, 1 BF16, 2 split-BF16x3.
+// precision: 0 FP64, 1 BF16, 2 split-BF16x3, 3 Ozaki-scheme FP64 emulation
+// on INT8 (block Hamiltonian pairs stay FP64 in 1-3).
 void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision, hipStream_t s);
 void prepare_bf16(SigmaPlan& plan, hipStream_t s);
+// Slices per operand (kappa digits, DMRG_OZAKI_SLICES, default 6) and the
+// Ozaki task lists of both stages.
+void prepare_ozaki(SigmaPlan& plan, hipStream_t s);
+int ozaki_kappa();
 
 }  // namespace dmrg
