@@ -112,6 +112,8 @@ def main():
                     help="FP64 sigma steps timed beside the headline precision (0: skip)")
     ap.add_argument("--dav-iters", type=int, default=4,
                     help="Davidson iterations timed with the mixed ladder (0: skip)")
+    ap.add_argument("--ozaki-steps", type=int, default=2,
+                    help="Ozaki-scheme (FP64 emulated on INT8) sigma steps timed beside the headline (0: skip)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch each sigma kernel by kernel instead of replaying a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -238,6 +240,31 @@ def main():
                "residual": r["residual"]}
         log(f"[bench] davidson {r['iterations']} iterations: {r['time_ms']:.0f} ms total, "
             f"{other:.2f} ms non-sigma per step -> step {ms + other:.1f} ms")
+    # Ozaki-scheme sigma: FP64 accuracy from INT8 MFMA digit products
+    ozaki = None
+    if args.ozaki_steps > 0:
+        soz = torch.empty_like(psi)
+        t_oz, kto, _ = timed_sigma("ozaki", args.ozaki_steps, 1, soz, True)
+        ms_oz = float(np.median(t_oz))
+        info_oz = ctx.sigma_info("ozaki")
+        kap = int(round((np.sqrt(8 * info_oz["hw_flops"] / info["flops"] + 1) - 1) / 2))
+        ms_gemm = (kto["ms_stage1"] + kto["ms_stage2"]) / max(1, kto["calls"])
+        int8_tops = info_oz["hw_flops"] * (info["flops"] - kto["flops_pinned"]) / info["flops"] / (ms_gemm * 1e-3) / 1e12
+        rel_oz = float((torch.linalg.norm(soz - ref) / torch.linalg.norm(ref)).item())
+        e_oz = float(torch.dot(psi, soz).item())
+        ozaki = {"slices": kap, "bits": 8 * kap - 1, "ms": ms_oz,
+                 "tflops": info["flops"] / (ms_oz * 1e-3) / 1e12,
+                 "speedup_vs_fp64": fp64["ms"] / ms_oz if fp64 else None,
+                 "sigma_rel_err_vs_fp64": rel_oz, "rayleigh_diff": e_oz - e_ref,
+                 "stage1_ms": kto["ms_stage1"] / max(1, kto["calls"]),
+                 "stage2_ms": kto["ms_stage2"] / max(1, kto["calls"]),
+                 "slicing_ms": kto["ms_convert"] / max(1, kto["calls"]),
+                 "pinned_fp64_ms": kto["ms_pinned"] / max(1, kto["calls"]),
+                 "int8_tops": int8_tops, "int8_peak_tops": 5000.0, "int8_frac": int8_tops / 5000.0}
+        log(f"[bench] sigma ozaki ({kap} slices, {8 * kap - 1} bits): median {ms_oz:.1f} ms "
+            f"({ozaki['tflops']:.1f} TFLOP/s FP64-equivalent), stage1 {ozaki['stage1_ms']:.1f} + stage2 "
+            f"{ozaki['stage2_ms']:.1f} + slicing {ozaki['slicing_ms']:.1f} + pinned {ozaki['pinned_fp64_ms']:.1f} ms; "
+            f"INT8 {int8_tops:.0f} TOP/s; |dsigma|/|sigma| = {rel_oz:.2e}")
     cpu = None
     if not args.no_cpu_baseline:
         t_cpu, n_s, n_all, per = cpu_baseline(m, args.cpu_terms)
@@ -283,7 +310,8 @@ def main():
                    "speedup_vs_fp64": fp64["ms"] / ms if fp64 else None,
                    "bf16_launch_config": tuned if args.precision != "fp64" else None,
                    "graphs": not args.no_graphs,
-                   "davidson": dav},
+                   "davidson": dav,
+                   "ozaki": ozaki},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

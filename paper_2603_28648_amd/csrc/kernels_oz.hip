@@ -1,10 +1,11 @@
 // Ozaki-scheme FP64 emulation on gfx950 INT8 MFMA (see gemm_oz.h).
 //
-// k_slice_oz: one wave per operand row: the row maximum (wave reduction)
-// gives the exponent e with |x| < (127/128) 2^e, so that every rounded
+// k_slice_oz: one workgroup per operand, one wave per row: the row maximum
+// (wave reduction) gives the exponent e with |x| < (127/128) 2^e, so that
+// every rounded
 // X = round(x 2^(p - e)) has a kappa-digit signed base-256 expansion; the
-// digits are written as kappa int8 planes (one byte per entry, coalesced
-// along k).
+// digits are written as kappa int8 planes (four entries a lane, one 32-bit
+// store per plane, coalesced along k).
 //
 // k_gemm_oz: the task model of the other grouped GEMMs (one workgroup per
 // 64 x 64 output tile, a list of segments), four waves as 2 x 2 with 32 x 32
@@ -41,19 +42,12 @@ __device__ __forceinline__ i32x4 oz_frag(const int8_t* part, int row, int q) {
   return *reinterpret_cast<const i32x4*>(part + row * 64 + 16 * (q ^ oz_swz(row)));
 }
 
-__global__ void k_slice_oz(const SliceOp* __restrict__ ops, int nops, int64_t rows, int8_t* arena,
-                           int32_t* exps, int kappa) {
+__global__ void k_slice_oz(const SliceOp* __restrict__ ops, int8_t* arena, int32_t* exps, int kappa) {
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   const int P = 8 * kappa - 1;
-  for (int64_t r = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); r < rows; r += (int64_t)gridDim.x * wpb) {
-    int lo = 0, hi = nops - 1;  // last op with row0 <= r (ops without rows are never picked)
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (ops[mid].row0 <= r) lo = mid; else hi = mid - 1;
-    }
-    const SliceOp op = ops[lo];
-    const int i = (int)(r - op.row0);
+  const SliceOp op = ops[blockIdx.x];  // one workgroup per operand, its waves over the rows
+  for (int i = threadIdx.x >> 6; i < op.rows; i += wpb) {
     auto x_at = [&](int kk) -> double {
       return op.colmajor ? op.src[(int64_t)kk * op.ld + i] : op.src[(int64_t)i * op.ld + kk];
     };
@@ -64,14 +58,24 @@ __global__ void k_slice_oz(const SliceOp* __restrict__ ops, int nops, int64_t ro
     // |x| <= mx < (127/128) 2^e keeps X inside the kappa-digit range
     const int e = mx > 0.0 ? ilogb(mx * (128.0 / 127.0)) + 1 : 0;
     if (lane == 0) exps[op.exp + i] = e;
+    // four consecutive entries a lane: one 32-bit store per digit plane
     int8_t* row = arena + op.dst + (int64_t)i * op.kp;
-    for (int kk = lane; kk < op.kp; kk += 64) {
-      const double x = kk < op.k ? x_at(kk) : 0.0;
-      int64_t X = (int64_t)rint(ldexp(x, P - e));
+    for (int k4 = 4 * lane; k4 < op.kp; k4 += 256) {
+      int64_t X[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double x = k4 + u < op.k ? x_at(k4 + u) : 0.0;
+        X[u] = (int64_t)rint(ldexp(x, P - e));
+      }
       for (int s = 0; s < kappa; ++s) {
-        const int64_t d = ((X + 128) & 255) - 128;
-        row[(int64_t)s * op.plane + kk] = (int8_t)d;
-        X = (X - d) >> 8;
+        uint32_t w = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t d = ((X[u] + 128) & 255) - 128;
+          w |= (uint32_t)(uint8_t)(int8_t)d << (8 * u);
+          X[u] = (X[u] - d) >> 8;
+        }
+        *reinterpret_cast<uint32_t*>(row + (int64_t)s * op.plane + k4) = w;
       }
     }
   }
@@ -258,8 +262,7 @@ void launch_slice_oz(const SliceOp* ops, int nops, int64_t rows, int8_t* arena, 
                      hipStream_t s) {
   if (rows <= 0 || nops <= 0) return;
   DMRG_REQUIRE(kappa >= kOzMinKappa && kappa <= kOzMaxKappa, kErrInvalidArg, "slice_oz: kappa out of range");
-  const int64_t g = std::max<int64_t>(1, std::min<int64_t>((rows + 3) / 4, 65536));
-  hipLaunchKernelGGL(k_slice_oz, dim3((unsigned)g), dim3(256), 0, s, ops, nops, rows, arena, exps, kappa);
+  hipLaunchKernelGGL(k_slice_oz, dim3((unsigned)nops), dim3(256), 0, s, ops, arena, exps, kappa);
   DMRG_HIP(hipGetLastError());
 }
 
