@@ -127,3 +127,20 @@ def test_ozaki_sigma_at_16_orbitals(ctx):
     print(f"  relative error {rel:.2e}, Rayleigh quotient difference {abs(eoz - e64):.2e}", flush=True)
     assert rel < 1e-12
     assert abs(eoz - e64) < 1e-10
+
+
+def test_ozaki_ladder_stage_in_davidson(ctx):
+    """An Ozaki stage in the Davidson ladder: same converged energy as FP64."""
+    import torch
+    print("davidson ladder ozaki -> fp64: K=8 N=8 D=20 window=3", flush=True)
+    h, eri, m = case(8, 8, 0, 20, 3)
+    lib_load(ctx, h, eri, m)
+    psi0 = torch.from_numpy(pack_psi(m.bonds, m.window, m.psi)).cuda()
+    x64 = psi0.clone()
+    r64 = ctx.davidson(x64, tol=1e-9, max_iter=200)
+    xoz = psi0.clone()
+    roz = ctx.davidson(xoz, tol=1e-9, max_iter=200, ladder=(("ozaki", 1e-7), ("fp64", None)))
+    torch.cuda.synchronize()
+    print(f"  E_fp64={r64['energy']:.12f} E_ladder={roz['energy']:.12f} sigma calls {roz['n_sigma']}", flush=True)
+    assert roz["n_sigma"]["ozaki"] > 0
+    assert abs(roz["energy"] - r64["energy"]) < 1e-10
