@@ -199,6 +199,7 @@ class Context:
                                      ctypes.byref(mps) if mps else None, int(site), int(direction),
                                      int(precision_mask))
         self._check(st, self.h)
+        self._window = int(site)
         return st
 
     def psi_size(self):
@@ -288,39 +289,81 @@ class Context:
         self._check(self.lib.dmrg_get_psi(self.h, _dev_ptr(out)), self.h)
         return out
 
+    def _half_sweeps(self, psi, n_half, max_bond_dim, tol, ladder, log):
+        """n_half half-sweeps from the loaded window; per half-sweep: energy of
+        its last window, lowest energy, largest truncation error, and the
+        seconds spent in the eigensolver and in operator construction."""
+        import time
+        import torch
+        K = self._n_orb
+        out = []
+        cur = psi
+        site = self._window
+        direction = -1 if site == K - 2 else +1
+        for _ in range(n_half):
+            e_last, e_min, eps_max, t_dav, t_build = None, np.inf, 0.0, 0.0, 0.0
+            while True:
+                t0 = time.perf_counter()
+                r = self.davidson(cur, tol=tol, ladder=ladder)
+                torch.cuda.synchronize()
+                t_dav += time.perf_counter() - t0
+                e_last = r["energy"]
+                e_min = min(e_min, e_last)
+                at_end = (direction > 0 and site == K - 2) or (direction < 0 and site == 0)
+                move = -direction if at_end else direction
+                eps, kept = self.truncate(cur, move, max_bond_dim)
+                eps_max = max(eps_max, eps)
+                site += move
+                t0 = time.perf_counter()
+                self.build_ops(site, move)
+                torch.cuda.synchronize()
+                t_build += time.perf_counter() - t0
+                cur = torch.empty(self.psi_size(), dtype=torch.float64, device=cur.device)
+                self.get_psi(cur)
+                if log:
+                    log(f"window {site - move} E={e_last:.12f} eps={eps:.2e} D={kept}")
+                if at_end:
+                    direction = move
+                    break
+            out.append({"energy": e_last, "min_energy": e_min, "max_trunc": eps_max,
+                        "davidson_s": t_dav, "build_s": t_build})
+        return out, cur
+
     def sweep(self, psi, n_sweeps, max_bond_dim, tol=1e-6, ladder=(("fp64", None),), log=None):
         """Two-site sweeps from the loaded window; returns per-half-sweep energies.
 
         psi: device tensor of the current window; the context's window must be
         0 (start of a left-to-right sweep).  Each half-sweep optimises every
         window once and turns at the chain end."""
-        import torch
-        K = self._n_orb
-        energies, trunc = [], []
+        halves, cur = self._half_sweeps(psi, 2 * n_sweeps, max_bond_dim, tol, ladder, log)
+        return [h["energy"] for h in halves], [h["max_trunc"] for h in halves], cur
+
+    def sweep_to_convergence(self, psi, max_bond_dim, sweep_tol=1e-5, max_sweeps=20, tol=1e-6,
+                             ladder=(("fp64", None),), log=None):
+        """Full sweeps (there and back) until the energies of three subsequent
+        sweeps agree within sweep_tol (the paper's stopping rule, 1e-5 Ha).
+        E_s is the lowest energy met in sweep s, eps_s its largest truncation
+        error.  Returns a dict with the per-sweep records, whether the rule was
+        met, and the final window vector.  log (optional) receives one line
+        per sweep."""
+        from .extrapolate import sweep_converged
+        sweeps = []
         cur = psi
-        site, direction = 0, +1
-        for sweep in range(2 * n_sweeps):
-            e_half = None
-            eps_max = 0.0
-            while True:
-                r = self.davidson(cur, tol=tol, ladder=ladder)
-                e_half = r["energy"]
-                at_end = (direction > 0 and site == K - 2) or (direction < 0 and site == 0)
-                move = -direction if at_end else direction
-                eps, kept = self.truncate(cur, move, max_bond_dim)
-                eps_max = max(eps_max, eps)
-                site += move
-                self.build_ops(site, move)
-                cur = torch.empty(self.psi_size(), dtype=torch.float64, device=cur.device)
-                self.get_psi(cur)
-                if log:
-                    log(f"half-sweep {sweep} window {site - move} E={e_half:.12f} eps={eps:.2e} D={kept}")
-                if at_end:
-                    direction = move
-                    break
-            energies.append(e_half)
-            trunc.append(eps_max)
-        return energies, trunc, cur
+        while len(sweeps) < max_sweeps:
+            halves, cur = self._half_sweeps(cur, 2, max_bond_dim, tol, ladder, None)
+            sweeps.append({"min_energy": min(h["min_energy"] for h in halves),
+                           "max_trunc": max(h["max_trunc"] for h in halves),
+                           "davidson_s": sum(h["davidson_s"] for h in halves),
+                           "build_s": sum(h["build_s"] for h in halves)})
+            if log:
+                sw = sweeps[-1]
+                log(f"sweep {len(sweeps)}: E={sw['min_energy']:.12f} eps={sw['max_trunc']:.2e} "
+                    f"eigensolver {sw['davidson_s']:.1f} s, operators {sw['build_s']:.1f} s")
+            if sweep_converged([sw["min_energy"] for sw in sweeps], sweep_tol):
+                break
+        converged = sweep_converged([sw["min_energy"] for sw in sweeps], sweep_tol)
+        return {"sweeps": sweeps, "converged": converged, "energy": sweeps[-1]["min_energy"],
+                "max_trunc": sweeps[-1]["max_trunc"], "psi": cur}
 
     def debug_diag(self, out):
         self._check(self.lib.dmrg_debug_diag(self.h, _dev_ptr(out)), self.h)

@@ -1,11 +1,10 @@
 // Ozaki-scheme FP64 emulation on gfx950 INT8 MFMA (see gemm_oz.h).
 //
-// k_slice_oz: one workgroup per operand, one wave per row: the row maximum
-// (wave reduction) gives the exponent e with |x| < (127/128) 2^e, so that
-// every rounded
-// X = round(x 2^(p - e)) has a kappa-digit signed base-256 expansion; the
-// digits are written as kappa int8 planes (four entries a lane, one 32-bit
-// store per plane, coalesced along k).
+// k_slice_oz: one workgroup per operand, each wave four rows at a time: the
+// row maximum (wave reduction) gives the exponent e with |x| < (127/128) 2^e,
+// so that every rounded X = round(x 2^(p - e)) has a kappa-digit signed
+// base-256 expansion; the digits are written as kappa int8 planes (four
+// entries a lane, one 32-bit store per plane, coalesced along k).
 //
 // k_gemm_oz: the task model of the other grouped GEMMs (one workgroup per
 // 64 x 64 output tile, a list of segments), four waves as 2 x 2 with 32 x 32
@@ -42,40 +41,76 @@ __device__ __forceinline__ i32x4 oz_frag(const int8_t* part, int row, int q) {
   return *reinterpret_cast<const i32x4*>(part + row * 64 + 16 * (q ^ oz_swz(row)));
 }
 
+// Digits of four consecutive entries (X: rounded integers) as one 32-bit
+// store per plane.
+__device__ __forceinline__ void oz_store_digits(int8_t* dst, int64_t plane, int kappa, int64_t X[4]) {
+  for (int s = 0; s < kappa; ++s) {
+    uint32_t w = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t d = ((X[u] + 128) & 255) - 128;
+      w |= (uint32_t)(uint8_t)(int8_t)d << (8 * u);
+      X[u] = (X[u] - d) >> 8;
+    }
+    *reinterpret_cast<uint32_t*>(dst + (int64_t)s * plane) = w;
+  }
+}
+
+// A wave takes kRows rows at once (their loads in flight together) and holds
+// up to kHeld entries of each row per lane (rows of up to 64 kHeld entries
+// are read once; longer rows read their remainder twice).
+constexpr int kRows = 4, kHeld = 8;
+
 __global__ void k_slice_oz(const SliceOp* __restrict__ ops, int8_t* arena, int32_t* exps, int kappa) {
   const int lane = threadIdx.x & 63;
-  const int wpb = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
   const int P = 8 * kappa - 1;
   const SliceOp op = ops[blockIdx.x];  // one workgroup per operand, its waves over the rows
-  for (int i = threadIdx.x >> 6; i < op.rows; i += wpb) {
-    auto x_at = [&](int kk) -> double {
-      return op.colmajor ? op.src[(int64_t)kk * op.ld + i] : op.src[(int64_t)i * op.ld + kk];
-    };
-    double mx = 0.0;
-    for (int kk = lane; kk < op.k; kk += 64) mx = fmax(mx, fabs(x_at(kk)));
+  auto x_at = [&](int i, int kk) -> double {
+    return op.colmajor ? op.src[(int64_t)kk * op.ld + i] : op.src[(int64_t)i * op.ld + kk];
+  };
+  // held entry q of a lane: k = 256 (q / 4) + 4 lane + q % 4
+  auto k_of = [&](int q) { return 256 * (q >> 2) + 4 * lane + (q & 3); };
+  for (int i0 = wave * kRows; i0 < op.rows; i0 += wpb * kRows) {
+    double v[kRows][kHeld], mx[kRows];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-    // |x| <= mx < (127/128) 2^e keeps X inside the kappa-digit range
-    const int e = mx > 0.0 ? ilogb(mx * (128.0 / 127.0)) + 1 : 0;
-    if (lane == 0) exps[op.exp + i] = e;
-    // four consecutive entries a lane: one 32-bit store per digit plane
-    int8_t* row = arena + op.dst + (int64_t)i * op.kp;
-    for (int k4 = 4 * lane; k4 < op.kp; k4 += 256) {
-      int64_t X[4];
+    for (int r = 0; r < kRows; ++r) {
+      const int i = i0 + r;
+      mx[r] = 0.0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double x = k4 + u < op.k ? x_at(k4 + u) : 0.0;
-        X[u] = (int64_t)rint(ldexp(x, P - e));
+      for (int q = 0; q < kHeld; ++q) {
+        const int kk = k_of(q);
+        v[r][q] = (i < op.rows && kk < op.k) ? x_at(i, kk) : 0.0;
+        mx[r] = fmax(mx[r], fabs(v[r][q]));
       }
-      for (int s = 0; s < kappa; ++s) {
-        uint32_t w = 0;
+      for (int kk = 64 * kHeld + lane; kk < op.k && i < op.rows; kk += 64) mx[r] = fmax(mx[r], fabs(x_at(i, kk)));
+    }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t d = ((X[u] + 128) & 255) - 128;
-          w |= (uint32_t)(uint8_t)(int8_t)d << (8 * u);
-          X[u] = (X[u] - d) >> 8;
-        }
-        *reinterpret_cast<uint32_t*>(row + (int64_t)s * op.plane + k4) = w;
+    for (int r = 0; r < kRows; ++r)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) mx[r] = fmax(mx[r], __shfl_xor(mx[r], off));
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const int i = i0 + r;
+      if (i >= op.rows) break;
+      // |x| <= mx < (127/128) 2^e keeps X inside the kappa-digit range
+      const int e = mx[r] > 0.0 ? ilogb(mx[r] * (128.0 / 127.0)) + 1 : 0;
+      if (lane == 0) exps[op.exp + i] = e;
+      int8_t* row = arena + op.dst + (int64_t)i * op.kp;
+#pragma unroll
+      for (int h = 0; h < kHeld / 4; ++h) {
+        const int k4 = 256 * h + 4 * lane;
+        if (k4 >= op.kp) break;
+        int64_t X[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) X[u] = (int64_t)rint(ldexp(v[r][4 * h + u], P - e));
+        oz_store_digits(row + k4, op.plane, kappa, X);
+      }
+      for (int k4 = 64 * kHeld + 4 * lane; k4 < op.kp; k4 += 256) {
+        int64_t X[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) X[u] = (int64_t)rint(ldexp(k4 + u < op.k ? x_at(i, k4 + u) : 0.0, P - e));
+        oz_store_digits(row + k4, op.plane, kappa, X);
       }
     }
   }
