@@ -14,20 +14,25 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // One workgroup (4 waves) per 64x64 output tile; each wave owns a 32x32
 // quarter as 2x2 blocks of v_mfma_f64_16x16x4f64.  Operands are staged
 // through LDS in k-slabs of 16 with bounds-checked (zero-filled) loads, so
-// ragged m, n, k need no padding in memory.  alpha is folded into A.
+// ragged m, n, k need no padding in memory.  alpha is folded into A.  The
+// slabs of all segments of a tile form one sequence, double-buffered: the
+// global loads of the next slab are issued into registers before the MFMAs
+// of the current one, then stored into the other LDS buffer (one barrier per
+// slab).
 //
 // MFMA operand layout (16x16x4 f64, wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; accumulator element v of lane l holds D[4*v + l/16][l%16]
 // (rows interleaved across the four 16-lane groups).
 constexpr int kTK = 16;
+constexpr int kLoadsA = (kTileM * kTK) / 256, kLoadsB = (kTileN * kTK) / 256;
 
 // ROLE only names the kernel for profilers: 0 = operator construction,
 // 1 = sigma stage 1 (psi x right operator), 2 = sigma stage 2 (left operator x T).
 template <int ROLE>
 __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ tiles,
                                                    const GemmSeg* __restrict__ segs) {
-  __shared__ double As[kTK][kTileM + 1];
-  __shared__ double Bs[kTK][kTileN + 1];
+  __shared__ double As[2][kTK][kTileM + 1];
+  __shared__ double Bs[2][kTK][kTileN + 1];
   const GemmTile t = tiles[blockIdx.x];
   if (t.m <= 0) return;  // padding tile of the XCD-ordered launch
   const int tid = threadIdx.x;
@@ -38,15 +43,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  for (int s = t.seg_begin; s < t.seg_end; ++s) {
-    const GemmSeg g = segs[s];
-    const double* __restrict__ A = static_cast<const double*>(g.a);
-    const double* __restrict__ B = static_cast<const double*>(g.b);
-    const bool ta = g.flags & kTransA, tb = g.flags & kTransB;
-    const double al = g.alpha;
-    for (int k0 = 0; k0 < g.k; k0 += kTK) {
+  if (t.seg_begin < t.seg_end) {
+    double ra[kLoadsA], rb[kLoadsB];
+    // global loads of the slab at k offset k0 of segment g into ra, rb
+    auto load = [&](const GemmSeg& g, int k0) {
+      const double* __restrict__ A = static_cast<const double*>(g.a);
+      const double* __restrict__ B = static_cast<const double*>(g.b);
+      const bool ta = g.flags & kTransA, tb = g.flags & kTransB;
 #pragma unroll
-      for (int r = 0; r < (kTileM * kTK) / 256; ++r) {
+      for (int r = 0; r < kLoadsA; ++r) {
         const int e = r * 256 + tid;
         int i, kk;
         if (!ta) { i = e / kTK; kk = e % kTK; }
@@ -57,10 +62,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
           const int64_t gi = (int64_t)t.row0 + i;
           v = ta ? A[(int64_t)gk * g.lda + gi] : A[gi * g.lda + gk];
         }
-        As[kk][i] = v * al;
+        ra[r] = v * g.alpha;
       }
 #pragma unroll
-      for (int r = 0; r < (kTileN * kTK) / 256; ++r) {
+      for (int r = 0; r < kLoadsB; ++r) {
         const int e = r * 256 + tid;
         int j, kk;
         if (!tb) { kk = e / kTileN; j = e % kTileN; }
@@ -71,21 +76,59 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
           const int64_t gj = (int64_t)t.col0 + j;
           v = tb ? B[gj * g.ldb + gk] : B[(int64_t)gk * g.ldb + gj];
         }
-        Bs[kk][j] = v;
+        rb[r] = v;
       }
-      __syncthreads();
+    };
+    // ra, rb into LDS buffer buf (same element placement as the loads)
+    auto store = [&](const GemmSeg& g, int buf) {
+      const bool ta = g.flags & kTransA, tb = g.flags & kTransB;
+#pragma unroll
+      for (int r = 0; r < kLoadsA; ++r) {
+        const int e = r * 256 + tid;
+        if (!ta) As[buf][e % kTK][e / kTK] = ra[r];
+        else As[buf][e / kTileM][e % kTileM] = ra[r];
+      }
+#pragma unroll
+      for (int r = 0; r < kLoadsB; ++r) {
+        const int e = r * 256 + tid;
+        if (!tb) Bs[buf][e / kTileN][e % kTileN] = rb[r];
+        else Bs[buf][e % kTK][e / kTK] = rb[r];
+      }
+    };
+    int s = t.seg_begin, k0 = 0, buf = 0;
+    GemmSeg g = segs[s];
+    load(g, 0);
+    store(g, 0);
+    __syncthreads();
+    while (true) {
+      // position of the next slab in the tile's sequence
+      int ns = s, nk0 = k0 + kTK;
+      GemmSeg ng = g;
+      if (nk0 >= g.k) {
+        nk0 = 0;
+        if (++ns < t.seg_end) ng = segs[ns];
+      }
+      const bool more = ns < t.seg_end;
+      if (more) load(ng, nk0);  // in flight during the MFMAs below
 #pragma unroll
       for (int kk = 0; kk < kTK; kk += 4) {
-        const double a0 = As[kk + lk][wm + lr];
-        const double a1 = As[kk + lk][wm + 16 + lr];
-        const double b0 = Bs[kk + lk][wn + lr];
-        const double b1 = Bs[kk + lk][wn + 16 + lr];
+        const double a0 = As[buf][kk + lk][wm + lr];
+        const double a1 = As[buf][kk + lk][wm + 16 + lr];
+        const double b0 = Bs[buf][kk + lk][wn + lr];
+        const double b1 = Bs[buf][kk + lk][wn + 16 + lr];
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
       }
+      if (!more) break;
+      // the other buffer was last read before the previous barrier
+      store(ng, buf ^ 1);
       __syncthreads();
+      buf ^= 1;
+      s = ns;
+      k0 = nk0;
+      g = ng;
     }
   }
   double* __restrict__ C = static_cast<double*>(t.c);
