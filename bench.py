@@ -112,6 +112,9 @@ def main():
                     help="FP64 sigma steps timed beside the headline precision (0: skip)")
     ap.add_argument("--dav-iters", type=int, default=4,
                     help="Davidson iterations timed with the mixed ladder (0: skip)")
+    ap.add_argument("--dav-solve", type=int, default=0,
+                    help="1: also solve to residual 1e-6 with the mixed ladder and with FP64 alone "
+                         "(time-to-solution and energy difference; minutes at CAS(54,36)); 0: skip")
     ap.add_argument("--ozaki-steps", type=int, default=2,
                     help="Ozaki-scheme (FP64 emulated on INT8) sigma steps timed beside the headline (0: skip)")
     ap.add_argument("--no-graphs", action="store_true",
@@ -240,6 +243,28 @@ def main():
                "residual": r["residual"]}
         log(f"[bench] davidson {r['iterations']} iterations: {r['time_ms']:.0f} ms total, "
             f"{other:.2f} ms non-sigma per step -> step {ms + other:.1f} ms")
+    # time to solution: the mixed ladder against FP64 alone, same start, residual 1e-6
+    solve = None
+    if args.dav_solve:
+        ladder = (("bf16", 1e-2), ("bf16x3", 1e-4), ("fp64", None))
+        res = {}
+        for name, lad in (("mixed", ladder), ("fp64", (("fp64", None),))):
+            x = psi.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with torch.cuda.stream(stream):
+                r = ctx.davidson(x, tol=1e-6, max_iter=400, ladder=lad)
+            stream.synchronize()
+            res[name] = {"time_s": time.perf_counter() - t0, "iterations": r["iterations"],
+                         "sigma_calls": r["n_sigma"], "energy": r["energy"], "residual": r["residual"],
+                         "converged": bool(r["converged"])}
+            log(f"[bench] davidson solve {name}: {res[name]['time_s']:.1f} s, {r['iterations']} iterations, "
+                f"sigma calls {r['n_sigma']}, E={r['energy']:.10f}, residual {r['residual']:.1e}")
+        solve = {"tol": 1e-6, "ladder": [list(x) for x in ladder], **res,
+                 "energy_diff": res["mixed"]["energy"] - res["fp64"]["energy"],
+                 "speedup": res["fp64"]["time_s"] / res["mixed"]["time_s"]}
+        log(f"[bench] time to solution: mixed {res['mixed']['time_s']:.1f} s vs FP64 {res['fp64']['time_s']:.1f} s "
+            f"({solve['speedup']:.2f}x), |E_mixed - E_FP64| = {abs(solve['energy_diff']):.1e}")
     # Ozaki-scheme sigma: FP64 accuracy from INT8 MFMA digit products
     ozaki = None
     if args.ozaki_steps > 0:
@@ -311,6 +336,7 @@ def main():
                    "bf16_launch_config": tuned if args.precision != "fp64" else None,
                    "graphs": not args.no_graphs,
                    "davidson": dav,
+                   "davidson_solve": solve,
                    "ozaki": ozaki},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
