@@ -407,7 +407,9 @@ dmrg_status dmrg_debug_diag(dmrg_ctx c, double* out) {
 
 dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* out) {
   if (!c || !out) return fail(c, kErrInvalidArg, "NULL argument");
-  if (!c->plan) return fail(c, kErrState, "sigma_get_info: call dmrg_build_ops first");
+  return guarded(c, [&]() -> dmrg_status {
+  DMRG_REQUIRE(c->plan, kErrState, "sigma_get_info: call dmrg_build_ops first");
+  DMRG_REQUIRE(precision >= 0 && precision <= 3, kErrInvalidArg, "sigma_get_info: unknown precision");
   std::memset(out, 0, sizeof(*out));
   const SigmaPlan& p = *c->plan;
   out->flops = p.flops;
@@ -434,6 +436,7 @@ dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* 
   for (auto& kv : c->right) out->operator_bytes += (int64_t)kv.second->bytes();
   if (p.psums) out->operator_bytes += (int64_t)p.psums->bytes();
   return kOk;
+  });
 }
 
 dmrg_status dmrg_sigma_graphs(dmrg_ctx c, int32_t enable) {
