@@ -125,7 +125,8 @@ dmrg_status dmrg_sigma(dmrg_ctx ctx, const double* psi, double* sigma, int32_t p
 
 typedef struct {
   double flops;          /* algorithmic FLOPs of one sigma (2*m*n*k over block GEMMs) */
-  double hw_flops;       /* MFMA FLOPs issued (3x flops for DMRG_BF16X3) */
+  double hw_flops;       /* MFMA operations issued: flops, 3x flops for DMRG_BF16X3,
+                            kappa (kappa + 1) / 2 x flops INT8 operations for DMRG_OZAKI */
   int64_t n_pairs;       /* operator pairs (left op, site matrix, right op) */
   int64_t n_right_ops;   /* distinct right operators contracted first */
   int64_t n_stage1_tiles, n_stage2_tiles, n_stage2_segments;
@@ -179,8 +180,10 @@ dmrg_status dmrg_sigma_timing(dmrg_ctx ctx, int32_t mode, dmrg_sigma_times* out)
  * the Numerical-procedure section's eigensolver tolerance is a residual
  * norm, here ||H_eff u - theta u||_2 with ||u||_2 = 1).  Sigma products run
  * through a precision ladder: stage s uses ladder[s] until the residual is
- * below ladder_tol[s] or stalls, then the subspace restarts from the Ritz
- * vector; the last stage must be DMRG_FP64 and runs to tol.  Orthogonalisation
+ * below ladder_tol[s], reaches 3x the floor its sigma error allows (relative
+ * sigma error 4e-3 BF16, 3e-6 split-BF16x3, 1e-13 Ozaki, times |theta|) or
+ * gains less than 10% in 10 iterations; then the subspace restarts from the
+ * Ritz vector; the last stage must be DMRG_FP64 and runs to tol.  Orthogonalisation
  * and the subspace matrices are FP64.  energy_out = FP64 Rayleigh quotient
  * + e_core.  psi_inout: start vector in, normalised Ritz vector out.
  * Returns DMRG_WARN_NOT_CONVERGED (with the best vector and energy) when
@@ -190,7 +193,7 @@ typedef struct {
   int32_t max_subspace;  /* 3..64 (default 24) */
   double tol;            /* default 1e-6 */
   int32_t n_ladder;      /* 1..4 */
-  int32_t ladder[4];     /* DMRG_FP64 / DMRG_BF16 / DMRG_BF16X3 per stage */
+  int32_t ladder[4];     /* DMRG_FP64 / DMRG_BF16 / DMRG_BF16X3 / DMRG_OZAKI per stage */
   double ladder_tol[4];  /* stage-end residuals (all stages but the last) */
   int32_t precondition;  /* 2: Olsen-corrected diag(H_eff) (recommended), 1: plain diag(H_eff), 0: none */
   int32_t restart;       /* Ritz vectors kept at a thick restart (default 6) */
