@@ -110,6 +110,8 @@ def main():
                     help="precision of the timed sigma steps (the mixed path by default)")
     ap.add_argument("--fp64-steps", type=int, default=3,
                     help="FP64 sigma steps timed beside the headline precision (0: skip)")
+    ap.add_argument("--bf16-steps", type=int, default=3,
+                    help="plain BF16 sigma steps timed beside the headline (0: skip)")
     ap.add_argument("--dav-iters", type=int, default=4,
                     help="Davidson iterations timed with the mixed ladder (0: skip)")
     ap.add_argument("--dav-solve", type=int, default=0,
@@ -229,6 +231,17 @@ def main():
     log(f"[bench] {kname}: {n_launch} launches, avg {ms_kernel:.3f} ms, stage1 "
         f"{kt['ms_stage1'] / kt['calls']:.1f} ms + stage2 {kt['ms_stage2'] / kt['calls']:.1f} ms + "
         f"pinned FP64 {kt['ms_pinned'] / kt['calls']:.1f} ms per sigma; {achieved:.1f} TFLOP/s")
+    # plain BF16 sigma (the first rung of the ladder)
+    bf16 = None
+    if args.bf16_steps > 0 and args.precision != "bf16":
+        sb = torch.empty_like(psi)
+        tb, _, _ = timed_sigma("bf16", args.bf16_steps, 1, sb, False)
+        rel_b = float((torch.linalg.norm(sb - ref) / torch.linalg.norm(ref)).item())
+        bf16 = {"ms": float(np.median(tb)), "tflops": info["flops"] / (np.median(tb) * 1e-3) / 1e12,
+                "sigma_rel_err_vs_fp64": rel_b}
+        bf16["frac_of_bf16_peak"] = bf16["tflops"] / PEAK_TFLOPS["bf16"]
+        log(f"[bench] sigma bf16: median {bf16['ms']:.2f} ms ({bf16['tflops']:.1f} TFLOP/s, "
+            f"{100 * bf16['frac_of_bf16_peak']:.1f}% of the BF16 peak); |dsigma|/|sigma| = {rel_b:.2e}")
     # Davidson step time with the mixed ladder (FP64 vectors and subspace)
     dav = None
     if args.dav_iters > 0:
@@ -330,6 +343,7 @@ def main():
         "data": "synthetic (seeded integral recipe, converged-like random MPS)",
         "config": {"workload": f"{args.config}: K={K} N={N} 2Sz={tsz} D={D} window=({i},{i + 1})",
                    "psi_size": m.psi_size(), "sigma_flops": info["flops"],
+                   "sigma_flops_stages": [info["flops_stage1"], info["flops_stage2"]],
                    "pairs": info["n_pairs"], "precision": args.precision,
                    "build_ops_s": round(t_build, 2), "wall_s_timed": round(t_wall, 3),
                    "rayleigh": e_mix, "rayleigh_fp64": e_ref, "rayleigh_diff": e_mix - e_ref,
@@ -339,6 +353,7 @@ def main():
                    "speedup_vs_fp64": fp64["ms"] / ms if fp64 else None,
                    "bf16_launch_config": tuned if args.precision != "fp64" else None,
                    "graphs": not args.no_graphs,
+                   "bf16_sigma": bf16,
                    "davidson": dav,
                    "davidson_solve": solve,
                    "ozaki": ozaki},
