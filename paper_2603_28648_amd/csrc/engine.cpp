@@ -960,8 +960,31 @@ static int mixed_shape(int m, int n) {
   return best;
 }
 
+// Parts of a problem edge of length m in the split configuration: whole
+// 128-blocks on 128-wide tiles, and a remainder of at most 64 on a 64-wide
+// tile (a longer remainder stays on a 128-wide tile).  Returns the count;
+// part p covers [lo[p], hi[p]), wide[p] = 1 for 128-wide tiles.
+static int split_parts(int m, int (&lo)[2], int (&hi)[2], int (&wide)[2]) {
+  const int rem = m % 128;
+  lo[0] = 0;
+  hi[0] = m;
+  wide[0] = m > 64;
+  if (m <= 64 || rem == 0 || rem > 64) return 1;
+  hi[0] = m - rem;
+  lo[1] = m - rem;
+  hi[1] = m;
+  wide[1] = 0;
+  return 2;
+}
+
+static int split_shape(int wide_rows, int wide_cols) {
+  if (wide_rows) return wide_cols ? kShape128x128s3 : kShape128x64;
+  return wide_cols ? kShape64x128 : kShape64x64;
+}
+
 // BF16 descriptors of one stage (all chunks) for one launch configuration:
-// tile shape (one for every problem, or kShapeMixed: per problem), locality
+// tile shape (one for every problem, kShapeMixed: per problem, or
+// kShapeSplit: per part of a problem), locality
 // grouping of the tiles (0: each problem its own group, 1: the problems of
 // one key together) and segment order (1: each problem's segments sorted by
 // their A operand).  out[chunk] holds one launch per tile shape used.
@@ -985,8 +1008,29 @@ static void build_bf_stage(SigmaPlan& plan, int stage, const BfChoice& ch,
       std::vector<int> keys;
       std::vector<int64_t> perm;
       for (size_t q : order) {
-        if (pshape[q] != sh) continue;
         const AProb& pb = A.probs[q];
+        // regions of this problem tiled by this launch: rows [r0, r1) x columns [c0, c1)
+        int reg[4][4], nreg = 0;
+        if (ch.shape == kShapeSplit) {
+          int rl[2], rh[2], rw[2], cl[2], chh[2], cw[2];
+          const int nr = split_parts(pb.m, rl, rh, rw), nc = split_parts(pb.n, cl, chh, cw);
+          for (int i = 0; i < nr; ++i)
+            for (int j = 0; j < nc; ++j)
+              if (split_shape(rw[i], cw[j]) == sh) {
+                reg[nreg][0] = rl[i];
+                reg[nreg][1] = rh[i];
+                reg[nreg][2] = cl[j];
+                reg[nreg][3] = chh[j];
+                ++nreg;
+              }
+        } else if (pshape[q] == sh) {
+          reg[0][0] = 0;
+          reg[0][1] = pb.m;
+          reg[0][2] = 0;
+          reg[0][3] = pb.n;
+          nreg = 1;
+        }
+        if (nreg == 0) continue;
         const size_t s0 = b.segs.size();
         perm.clear();
         for (int64_t k = pb.s0; k < pb.s1; ++k) perm.push_back(k);
@@ -1002,11 +1046,14 @@ static void build_bf_stage(SigmaPlan& plan, int stage, const BfChoice& ch,
           b.segs.push_back({bfp(g.a), bfp(g.b), plan.bufs[g.a.buf].n, plan.bufs[g.b.buf].n, g.lda,
                             g.ldb, g.k, g.flags, g.alpha});
         }
-        if (stage == 1)
-          b.add_problem(bfp(pb.c), plan.bufs[pb.c.buf].n, pb.ldc, pb.m, pb.n, s0, b.segs.size(), 0);
-        else
-          b.add_problem(plan.bufs[pb.c.buf].f64 + pb.c.off, 0, pb.ldc, pb.m, pb.n, s0, b.segs.size(),
-                        pb.beta);
+        for (int r = 0; r < nreg; ++r) {
+          if (stage == 1)
+            b.add_region(bfp(pb.c), plan.bufs[pb.c.buf].n, pb.ldc, reg[r][0], reg[r][1], reg[r][2],
+                         reg[r][3], s0, b.segs.size(), 0);
+          else
+            b.add_region(plan.bufs[pb.c.buf].f64 + pb.c.off, 0, pb.ldc, reg[r][0], reg[r][1], reg[r][2],
+                         reg[r][3], s0, b.segs.size(), pb.beta);
+        }
         keys.resize(b.tiles.size(), ch.order == 1 ? pb.key : (int)q);
       }
       if (b.tiles.empty()) continue;
@@ -1245,7 +1292,7 @@ static void autotune_bf16(SigmaPlan& plan, hipStream_t s) {
       plan.tune_log.push_back({stage, c, t});
       if (t < tbest) { tbest = t; best = c; }
     };
-    for (int sh = 0; sh <= kShapeMixed; ++sh) trial(BfChoice{sh, 0, 0});
+    for (int sh = 0; sh <= kShapeSplit; ++sh) trial(BfChoice{sh, 0, 0});
     const int sh = best.shape;
     trial(BfChoice{sh, 1, 0});
     if (stage == 2) {
@@ -1286,12 +1333,12 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
       b.shape = c[k] & 15;
       b.order = (c[k] >> 4) & 15;
       b.sort_a = (c[k] >> 8) & 1;
-      DMRG_REQUIRE(c[k] >= 0 && b.shape <= kShapeMixed && b.order <= 1, kErrInvalidArg,
+      DMRG_REQUIRE(c[k] >= 0 && b.shape <= kShapeSplit && b.order <= 1, kErrInvalidArg,
                    "DMRG_BF16_CONFIG: unknown configuration code");
     }
   } else if (fixed) {
     const int sh = std::atoi(fixed);
-    DMRG_REQUIRE(sh >= 0 && sh <= kShapeMixed, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0 to 5");
+    DMRG_REQUIRE(sh >= 0 && sh <= kShapeSplit, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0 to 6");
     plan.bf_choice[0].shape = plan.bf_choice[1].shape = sh;
   } else if (env ? std::atoi(env) != 0 : plan.flops > 5e10) {
     autotune_bf16(plan, s);

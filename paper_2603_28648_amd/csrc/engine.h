@@ -335,8 +335,11 @@ struct SigmaTiming {
 
 // Launch configuration of the BF16 stages (chosen by the autotuner).
 constexpr int kShapeMixed = kNumShapes;  // tile shape chosen per output problem
+// 128 x 128 tiles over whole 128-blocks of each output problem; remainders
+// of at most 64 rows or columns on 64-wide tiles (one launch per shape)
+constexpr int kShapeSplit = kNumShapes + 1;
 struct BfChoice {
-  int shape = kShape128x64;  // tile shape, or kShapeMixed
+  int shape = kShape128x64;  // tile shape, kShapeMixed or kShapeSplit
   int order = 0;             // 0: per-problem XCD groups, 1: groups by locality key
   int sort_a = 0;            // 1: segments of a problem sorted by their A operand
 };

@@ -38,16 +38,22 @@ struct GemmBatchB {
   std::vector<GemmTileB> tiles;
   int shape = kShape128x64;  // tile of the NT kernel
   void add_problem(void* c, int64_t clo, int ldc, int m, int n, size_t s0, size_t s1, int beta) {
-    if (m <= 0 || n <= 0 || s1 <= s0) return;
+    add_region(c, clo, ldc, 0, m, 0, n, s0, s1, beta);
+  }
+  // Tiles over rows [r0, r1) and columns [q0, q1) of an output problem (the
+  // rest of the problem is tiled by other launches).
+  void add_region(void* c, int64_t clo, int ldc, int r0, int r1, int q0, int q1, size_t s0, size_t s1,
+                  int beta) {
+    if (r1 <= r0 || q1 <= q0 || s1 <= s0) return;
     const int TM = shape_rows(shape), TN = shape_cols(shape);
-    for (int r = 0; r < m; r += TM)
-      for (int q = 0; q < n; q += TN) {
+    for (int r = r0; r < r1; r += TM)
+      for (int q = q0; q < q1; q += TN) {
         GemmTileB t;
         t.c = c;
         t.clo = clo;
         t.ldc = ldc;
-        t.m = std::min(TM, m - r);
-        t.n = std::min(TN, n - q);
+        t.m = std::min(TM, r1 - r);
+        t.n = std::min(TN, q1 - q);
         t.row0 = r;
         t.col0 = q;
         t.seg_begin = (int32_t)s0;

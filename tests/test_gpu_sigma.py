@@ -75,7 +75,8 @@ def test_sigma_repeat_is_bitwise_deterministic(ctx):
 
 
 @pytest.mark.parametrize("K,N,tsz,D,i", [(8, 8, 0, 64, 3), (12, 12, 0, 256, 5), (10, 9, 1, 200, 2)])
-@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4", "5"])  # 128x64, 64x64, 64x128, 128x128 (2 or 3 LDS stages), per problem
+# 128x64, 64x64, 64x128, 128x128 (2 or 3 LDS stages), per problem, 128x128 with 64-wide edge tiles
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4", "5", "6"])
 def test_mixed_sigma_error_vs_fp64(ctx, monkeypatch, K, N, tsz, D, i, tile):
     """BF16 and split-BF16x3 sigma against the FP64 sigma of the same plan."""
     monkeypatch.setenv("DMRG_BF16_SHAPE", tile)
