@@ -115,9 +115,10 @@ def main():
     ap.add_argument("--dav-iters", type=int, default=4,
                     help="Davidson iterations timed with the mixed ladder (0: skip)")
     ap.add_argument("--dav-solve", type=int, default=0,
-                    help="1: also solve to residual 1e-6 with the mixed ladder and with FP64 alone "
-                         "(time-to-solution and energy difference; minutes at CAS(54,36)); "
-                         "2: the mixed ladder only; 0: skip")
+                    help="1: also solve to residual 1e-6 with the mixed ladder, with the mixed ladder "
+                         "and residual refinement, and with FP64 alone (time-to-solution and energy "
+                         "differences; minutes at CAS(54,36)); 2: the mixed ladder only; 3: the "
+                         "refined ladder only; 0: skip")
     ap.add_argument("--ozaki-steps", type=int, default=2,
                     help="Ozaki-scheme (FP64 emulated on INT8) sigma steps timed beside the headline (0: skip)")
     ap.add_argument("--no-graphs", action="store_true",
@@ -262,13 +263,14 @@ def main():
     if args.dav_solve:
         ladder = (("bf16", 1e-2), ("bf16x3", 1e-4), ("fp64", None))
         res = {}
-        runs = (("mixed", ladder), ("fp64", (("fp64", None),)))
-        for name, lad in runs[:1 if args.dav_solve == 2 else 2]:
+        runs = (("mixed", ladder, False), ("refined", ladder, True), ("fp64", (("fp64", None),), False))
+        runs = {1: runs, 2: runs[:1], 3: runs[1:2]}[args.dav_solve]
+        for name, lad, refine in runs:
             x = psi.clone()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             with torch.cuda.stream(stream):
-                r = ctx.davidson(x, tol=1e-6, max_iter=400, ladder=lad)
+                r = ctx.davidson(x, tol=1e-6, max_iter=400, ladder=lad, refine=refine)
             stream.synchronize()
             res[name] = {"time_s": time.perf_counter() - t0, "iterations": r["iterations"],
                          "sigma_calls": r["n_sigma"], "energy": r["energy"], "residual": r["residual"],
@@ -277,11 +279,12 @@ def main():
                 f"sigma calls {r['n_sigma']}, E={r['energy']:.10f}, residual {r['residual']:.1e}")
         solve = {"tol": 1e-6, "ladder": [list(x) for x in ladder], **res}
         if "fp64" in res:
-            solve["energy_diff"] = res["mixed"]["energy"] - res["fp64"]["energy"]
-            solve["speedup"] = res["fp64"]["time_s"] / res["mixed"]["time_s"]
-            log(f"[bench] time to solution: mixed {res['mixed']['time_s']:.1f} s vs FP64 "
-                f"{res['fp64']['time_s']:.1f} s ({solve['speedup']:.2f}x), "
-                f"|E_mixed - E_FP64| = {abs(solve['energy_diff']):.1e}")
+            for name in ("mixed", "refined"):
+                solve[f"energy_diff_{name}"] = res[name]["energy"] - res["fp64"]["energy"]
+                solve[f"speedup_{name}"] = res["fp64"]["time_s"] / res[name]["time_s"]
+                log(f"[bench] time to solution: {name} {res[name]['time_s']:.1f} s vs FP64 "
+                    f"{res['fp64']['time_s']:.1f} s ({solve[f'speedup_{name}']:.2f}x), "
+                    f"|E_{name} - E_FP64| = {abs(solve[f'energy_diff_{name}']):.1e}")
     # Ozaki-scheme sigma: FP64 accuracy from INT8 MFMA digit products
     ozaki = None
     if args.ozaki_steps > 0:

@@ -199,6 +199,15 @@ typedef struct {
   double ladder_tol[4];  /* stage-end residuals (all stages but the last) */
   int32_t precondition;  /* 2: Olsen-corrected diag(H_eff) (recommended), 1: plain diag(H_eff), 0: none */
   int32_t restart;       /* Ritz vectors kept at a thick restart (default 6) */
+  int32_t refine;        /* 1: when the ladder reaches its DMRG_FP64 stage from a reduced
+                            precision, residual refinement (Jacobi-Davidson with inexact inner
+                            solves): the FP64 stage keeps its subspace, FP64 sigma products
+                            and Rayleigh-Ritz, but each correction t solves
+                            (1 - u u^T)(H - theta)(1 - u u^T) t = -r (t orthogonal to u) for
+                            the Ritz pair (theta, u) and its FP64 residual r, by
+                            preconditioned conjugate gradients on the previous stage's
+                            reduced-precision sigma to 1e-2 relative (at most 60 products,
+                            each counted as an iteration).  0: off (default) */
 } dmrg_davidson_opts;
 
 typedef struct {

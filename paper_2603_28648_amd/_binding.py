@@ -58,7 +58,8 @@ class DavidsonOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("max_subspace", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("n_ladder", ctypes.c_int32),
                 ("ladder", ctypes.c_int32 * 4), ("ladder_tol", ctypes.c_double * 4),
-                ("precondition", ctypes.c_int32), ("restart", ctypes.c_int32)]
+                ("precondition", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("refine", ctypes.c_int32)]
 
 
 class SigmaTimes(ctypes.Structure):
@@ -250,16 +251,19 @@ class Context:
         return dh, deri
 
     def davidson(self, psi, tol=1e-6, max_iter=100, max_subspace=24,
-                 ladder=(("fp64", None),), precondition=2, restart=6):
+                 ladder=(("fp64", None),), precondition=2, restart=6, refine=False):
         """Lowest eigenpair at the current window; psi (device) is updated in place.
 
         ladder: sequence of (precision, stage-end residual); the last stage
-        must be fp64 (its threshold is tol)."""
+        must be fp64 (its threshold is tol).  refine: in the last stage, each
+        correction vector solves the Jacobi-Davidson correction equation for
+        the FP64 residual with the previous stage's reduced precision."""
         o = DavidsonOpts()
         o.max_iter, o.max_subspace, o.tol = int(max_iter), int(max_subspace), float(tol)
         o.n_ladder = len(ladder)
         o.precondition = int(precondition)
         o.restart = int(restart)
+        o.refine = int(bool(refine))
         for k, (p, t) in enumerate(ladder):
             o.ladder[k] = PRECISIONS[p] if isinstance(p, str) else int(p)
             o.ladder_tol[k] = float(t) if t is not None else 0.0

@@ -312,6 +312,7 @@ dmrg_status dmrg_davidson(dmrg_ctx c, double* psi, const dmrg_davidson_opts* opt
     o.n_ladder = opts->n_ladder;
     o.precondition = opts->precondition;
     if (opts->restart > 0) o.restart = opts->restart;
+    o.refine = opts->refine != 0;
     DMRG_REQUIRE(o.max_iter >= 0 && o.max_subspace >= 3 && o.max_subspace <= 64, kErrInvalidArg,
                  "davidson: need max_iter >= 0 and 3 <= max_subspace <= 64");
     DMRG_REQUIRE(o.tol > 0, kErrInvalidArg, "davidson: tol must be positive");

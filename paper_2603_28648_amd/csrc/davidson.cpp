@@ -33,6 +33,10 @@ double sigma_rel_error(int precision) {
 }
 constexpr double kFloorFactor = 3.0;
 constexpr int kStallWindow = 10;
+// Residual refinement: relative reduction of the correction equation's
+// residual that ends an inner solve, and the inner iterations allowed.
+constexpr double kRefineEta = 1e-2;
+constexpr int kRefineInner = 60;
 }  // namespace
 
 void launch_extract_diag(const DiagTask* tasks, int ntasks, hipStream_t s);
@@ -207,6 +211,69 @@ int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult
   const bool verbose = std::getenv("DMRG_VERBOSE") != nullptr;  // one progress line per iteration
   const int nst = std::max(1, o.n_ladder);
   auto prec_of = [&](int st) { return o.n_ladder > 0 ? o.ladder[st] : 0; };
+  // Residual refinement after a reduced-precision stage (Jacobi-Davidson
+  // with inexact inner solves): the FP64 stage keeps its Davidson subspace,
+  // FP64 sigma products and Rayleigh-Ritz, but each correction vector t
+  // solves the correction equation
+  //   (1 - u u^T)(H - theta)(1 - u u^T) t = -r,  t orthogonal to u,
+  // for the Ritz pair (theta, u) and FP64 residual r, by conjugate gradients
+  // on the reduced-precision sigma with the diagonal preconditioner
+  // (diag(H_eff) - theta, projected), to a relative residual of kRefineEta
+  // (looser when |r| is within a few times tol).
+  // The reduced-precision error limits how much each correction gains, not
+  // the attainable residual, which the FP64 products set.
+  DevBuf cgb;
+  auto inner_cg = [&](double* x, int lp, double theta_, int& iters_) {
+    if (!cgb.p) cgb.alloc((size_t)4 * n * sizeof(double));
+    double* rs = cgb.as<double>();  // residual of the correction equation
+    double* z = rs + n;             // preconditioned residual
+    double* p = z + n;              // search direction
+    double* q = p + n;              // projected (H - theta) p
+    auto project = [&](double* v) { launch_axpy(v, -dot(u, v), u, n, s); };
+    const bool below_ = theta_ < dmin;
+    auto precond = [&]() {  // z = P (diag - theta)^-1 rs, or P rs
+      if (o.precondition > 0 && below_) {
+        launch_precondition(z, rs, d, theta_, n, s);
+        launch_scale(z, -1.0, n, s);
+      } else {
+        DMRG_HIP(hipMemcpyAsync(z, rs, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      }
+      project(z);
+    };
+    DMRG_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+    DMRG_HIP(hipMemcpyAsync(rs, r, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_scale(rs, -1.0, n, s);
+    project(rs);
+    precond();
+    DMRG_HIP(hipMemcpyAsync(p, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double rz = dot(rs, z);
+    const double r0 = std::sqrt(std::max(0.0, dot(rs, rs)));
+    // near the target a looser solve suffices: the correction needs to cut
+    // the residual only to a fraction of tol
+    const double eta = std::max(kRefineEta, std::min(0.5, 0.3 * o.tol / std::max(r0, 1e-300)));
+    for (int it = 0; it < kRefineInner && iters_ < o.max_iter; ++it) {
+      ++iters_;
+      sigma(p, q, lp);
+      launch_axpy(q, -theta_, p, n, s);
+      project(q);
+      const double pq = dot(p, q);
+      if (!(pq > 0) || !(rz > 0)) break;  // the projected operator is not positive here
+      const double alpha = rz / pq;
+      launch_axpy(x, alpha, p, n, s);
+      launch_axpy(rs, -alpha, q, n, s);
+      const double rsn = std::sqrt(std::max(0.0, dot(rs, rs)));
+      if (verbose)
+        fprintf(stderr, "[dmrg] refinement inner %d (precision %d): relative residual %.3e\n", it, lp,
+                rsn / r0);
+      if (rsn < eta * r0) break;
+      precond();
+      const double rz1 = dot(rs, z);
+      launch_scale(p, rz1 / rz, n, s);
+      launch_axpy(p, 1.0, z, n, s);
+      rz = rz1;
+    }
+  };
+  int refine_lp = -1;  // reduced precision of the inner solves, once refining
   sigma(V, W, prec_of(stage));
   int k = 1;
   fill_col(0);
@@ -257,6 +324,7 @@ int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult
       // next ladder stage: restart from the Ritz vector with a fresh sigma
       ++stage;
       hist.clear();
+      if (o.refine && stage == nst - 1 && prec_of(stage - 1) != 0) refine_lp = prec_of(stage - 1);
       const double un = std::sqrt(dot(u, u));
       DMRG_HIP(hipMemcpyAsync(V, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
       launch_scale(V, 1.0 / un, n, s);
@@ -273,7 +341,14 @@ int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult
     // denominators pass through zero and the correction is dominated by
     // the few components where diag ~ theta, so those steps take t = r.
     const bool below = theta < dmin;
-    if (o.precondition == 2 && below) {
+    double tn0 = 0;
+    if (refine_lp >= 0) {
+      inner_cg(t, refine_lp, theta, iters);
+      tn0 = std::sqrt(std::max(0.0, dot(t, t)));
+    }
+    if (refine_lp >= 0 && tn0 > 0) {
+      // correction from the inner solve
+    } else if (o.precondition == 2 && below) {
       // Olsen: t = M^-1 (r - eps u), eps = u.M^-1 r / u.M^-1 u, M = theta - diag;
       // removes the component of M^-1 r along the Ritz vector that makes the
       // plain correction degenerate when diag(H_eff) is a good approximation

@@ -17,6 +17,7 @@ struct DavidsonOpts {
   int max_subspace = 24;
   int restart = 6;        // Ritz vectors kept at a thick restart
   int precondition = 2;   // 2: Olsen-corrected diag(H_eff), 1: plain diag, 0: none
+  int refine = 0;         // 1: residual refinement instead of FP64 Davidson after a reduced stage
   double tol = 1e-6;      // ||H u - theta u||_2 with ||u|| = 1, last ladder stage
   int n_ladder = 1;       // number of precision stages
   int ladder[4] = {0, 0, 0, 0};

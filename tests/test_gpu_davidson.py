@@ -71,3 +71,33 @@ def test_davidson_warns_when_iterations_run_out(ctx):
     r = ctx.davidson(_start(ctx, m), tol=1e-12, max_iter=2)
     assert r["status"] == 1 and not r["converged"]
     assert np.isfinite(r["energy"])
+
+
+@pytest.mark.parametrize("K,N,tsz,D,i", [(10, 9, 1, 200, 2), (12, 12, 0, 256, 5)])
+def test_refined_ladder_matches_oracle_eigenvalue(ctx, K, N, tsz, D, i):
+    """Split-BF16x3 Davidson, then residual refinement (FP64 residuals,
+    corrections solved on split-BF16x3 sigmas): the oracle's eigenvalue, with
+    a handful of FP64 sigma products."""
+    print(f"davidson bf16x3 + refinement K={K} D={D} vs oracle eigsh", flush=True)
+    h, eri, m = case(K, N, tsz, D, i)
+    lib_load(ctx, h, eri, m)
+    r = ctx.davidson(_start(ctx, m), tol=1e-7, max_iter=400,
+                     ladder=(("bf16x3", 1e-4), ("fp64", None)), refine=True)
+    e_ref = _oracle_lowest(h, eri, m)
+    print(f"  E={r['energy']:.12f} ref={e_ref:.12f} iters={r['iterations']} res={r['residual']:.2e} "
+          f"n_sigma={r['n_sigma']}", flush=True)
+    assert r["converged"] and r["residual"] < 1e-7
+    assert abs(r["energy"] - e_ref) < 1e-9 * max(1.0, abs(e_ref))
+    assert r["n_sigma"]["fp64"] <= 14
+
+
+def test_refined_full_ladder_matches_fp64(ctx):
+    print("davidson bf16 -> bf16x3 -> refinement K=14 D=400 vs FP64 Davidson", flush=True)
+    h, eri, m = case(14, 14, 0, 400, 6)
+    lib_load(ctx, h, eri, m)
+    r64 = ctx.davidson(_start(ctx, m), tol=1e-6, max_iter=400)
+    rrf = ctx.davidson(_start(ctx, m), tol=1e-6, max_iter=400, ladder=MIXED, refine=True)
+    print(f"  E64={r64['energy']:.12f} Erefined={rrf['energy']:.12f} n_sigma={rrf['n_sigma']} "
+          f"fp64 n_sigma={r64['n_sigma']}", flush=True)
+    assert r64["converged"] and rrf["converged"]
+    assert abs(rrf["energy"] - r64["energy"]) < 1e-6
