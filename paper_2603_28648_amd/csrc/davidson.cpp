@@ -2,7 +2,9 @@
 // the diagonal preconditioner and a precision ladder for the sigma products.
 //
 // Vectors live on the device in FP64; the subspace matrices (k <= 64) are
-// copied to the host and diagonalised by cyclic Jacobi.  Each ladder stage
+// diagonalised on the device in FP64 (rocSOLVER dsyevd), and their
+// eigenvectors are copied to the host, which picks the Ritz pair and the
+// restart combinations.  Each ladder stage
 // uses one sigma precision until the residual norm drops below the stage
 // threshold, reaches the floor that precision allows, or stalls; the
 // subspace is then restarted from the current Ritz vector with sigma
@@ -14,6 +16,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
+
+#include <rocsolver/rocsolver.h>
 
 #include "davidson.h"
 
@@ -110,48 +114,6 @@ void build_diagonal(SigmaPlan& plan, const Bond& bl, const Bond& br, hipStream_t
   DMRG_HIP(hipStreamSynchronize(s));
 }
 
-// ---- small dense symmetric eigensolver (cyclic Jacobi) ---------------------
-static void jacobi_eigh(int n, std::vector<double> A, std::vector<double>& w,
-                        std::vector<double>& V) {
-  V.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0, tot = 0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        tot += A[(size_t)i * n + j] * A[(size_t)i * n + j];
-        if (i != j) off += A[(size_t)i * n + j] * A[(size_t)i * n + j];
-      }
-    if (off <= 1e-30 * std::max(tot, 1e-300)) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[(size_t)p * n + q];
-        if (std::abs(apq) < 1e-300) continue;
-        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-        const double tau = (aqq - app) / (2 * apq);
-        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::abs(tau) + std::sqrt(1 + tau * tau));
-        const double c = 1 / std::sqrt(1 + t * t), s = t * c;
-        for (int k = 0; k < n; ++k) {
-          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-          A[(size_t)k * n + p] = c * akp - s * akq;
-          A[(size_t)k * n + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-          A[(size_t)p * n + k] = c * apk - s * aqk;
-          A[(size_t)q * n + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-          V[(size_t)k * n + p] = c * vkp - s * vkq;
-          V[(size_t)k * n + q] = s * vkp + c * vkq;
-        }
-      }
-  }
-  w.resize(n);
-  for (int i = 0; i < n; ++i) w[i] = A[(size_t)i * n + i];
-}
-
 static double now_ms() {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -179,6 +141,39 @@ int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult
     dmin = n > 0 ? *std::min_element(dh.begin(), dh.end()) : 0.0;
   }
   std::vector<double> G((size_t)kmax * kmax, 0.0), hh(64);
+  // subspace eigenproblem on the device: G_k (k x k) -> eigenvalues ascending
+  // in ev, eigenvector j in column j of Y (Y[i * k + j] = component i)
+  struct Solver {
+    rocblas_handle h = nullptr;
+    ~Solver() {
+      if (h) rocblas_destroy_handle(h);
+    }
+  } solver;
+  DMRG_REQUIRE(rocblas_create_handle(&solver.h) == rocblas_status_success, kErrHip,
+               "davidson: rocblas_create_handle failed");
+  DMRG_REQUIRE(rocblas_set_stream(solver.h, s) == rocblas_status_success, kErrHip,
+               "davidson: rocblas_set_stream failed");
+  DevBuf eigA((size_t)kmax * kmax * sizeof(double)), eigD(kmax * sizeof(double)),
+      eigE(kmax * sizeof(double)), eigInfo(sizeof(rocblas_int));
+  std::vector<double> colmaj((size_t)kmax * kmax);
+  auto subspace_eigh = [&](int k, const std::vector<double>& Gk, std::vector<double>& ev_,
+                           std::vector<double>& Y_) {
+    DMRG_HIP(hipMemcpyAsync(eigA.p, Gk.data(), (size_t)k * k * sizeof(double), hipMemcpyHostToDevice, s));
+    DMRG_REQUIRE(rocsolver_dsyevd(solver.h, rocblas_evect_original, rocblas_fill_upper, k, eigA.as<double>(),
+                                  k, eigD.as<double>(), eigE.as<double>(),
+                                  eigInfo.as<rocblas_int>()) == rocblas_status_success,
+                 kErrHip, "davidson: rocsolver_dsyevd failed");
+    ev_.resize(k);
+    rocblas_int info = 0;
+    DMRG_HIP(hipMemcpyAsync(ev_.data(), eigD.p, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipMemcpyAsync(colmaj.data(), eigA.p, (size_t)k * k * sizeof(double), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipMemcpyAsync(&info, eigInfo.p, sizeof(info), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    DMRG_REQUIRE(info == 0, kErrHip, "davidson: subspace eigensolver did not converge");
+    Y_.resize((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < k; ++j) Y_[(size_t)i * k + j] = colmaj[(size_t)j * k + i];
+  };
   DevBuf tmpV, tmpW;
   std::vector<double> ev, Y;
   auto dot = [&](const double* a, const double* b) {
@@ -285,7 +280,7 @@ int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult
     std::vector<double> Gk((size_t)k * k);
     for (int i = 0; i < k; ++i)
       for (int j = 0; j < k; ++j) Gk[(size_t)i * k + j] = G[(size_t)i * kmax + j];
-    jacobi_eigh(k, Gk, ev, Y);
+    subspace_eigh(k, Gk, ev, Y);
     int imin = (int)(std::min_element(ev.begin(), ev.end()) - ev.begin());
     theta = ev[imin];
     std::vector<double> y(k);
