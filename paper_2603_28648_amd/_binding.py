@@ -293,7 +293,7 @@ class Context:
         self._check(self.lib.dmrg_get_psi(self.h, _dev_ptr(out)), self.h)
         return out
 
-    def _half_sweeps(self, psi, n_half, max_bond_dim, tol, ladder, log):
+    def _half_sweeps(self, psi, n_half, max_bond_dim, tol, ladder, log, refine=False):
         """n_half half-sweeps from the loaded window; per half-sweep: energy of
         its last window, lowest energy, largest truncation error, and the
         seconds spent in the eigensolver and in operator construction."""
@@ -308,7 +308,7 @@ class Context:
             e_last, e_min, eps_max, t_dav, t_build = None, np.inf, 0.0, 0.0, 0.0
             while True:
                 t0 = time.perf_counter()
-                r = self.davidson(cur, tol=tol, ladder=ladder)
+                r = self.davidson(cur, tol=tol, ladder=ladder, refine=refine)
                 torch.cuda.synchronize()
                 t_dav += time.perf_counter() - t0
                 e_last = r["energy"]
@@ -333,28 +333,30 @@ class Context:
                         "davidson_s": t_dav, "build_s": t_build})
         return out, cur
 
-    def sweep(self, psi, n_sweeps, max_bond_dim, tol=1e-6, ladder=(("fp64", None),), log=None):
+    def sweep(self, psi, n_sweeps, max_bond_dim, tol=1e-6, ladder=(("fp64", None),), log=None,
+              refine=False):
         """Two-site sweeps from the loaded window; returns per-half-sweep energies.
 
         psi: device tensor of the current window; the context's window must be
         0 (start of a left-to-right sweep).  Each half-sweep optimises every
         window once and turns at the chain end."""
-        halves, cur = self._half_sweeps(psi, 2 * n_sweeps, max_bond_dim, tol, ladder, log)
+        halves, cur = self._half_sweeps(psi, 2 * n_sweeps, max_bond_dim, tol, ladder, log, refine)
         return [h["energy"] for h in halves], [h["max_trunc"] for h in halves], cur
 
     def sweep_to_convergence(self, psi, max_bond_dim, sweep_tol=1e-5, max_sweeps=20, tol=1e-6,
-                             ladder=(("fp64", None),), log=None):
+                             ladder=(("fp64", None),), log=None, refine=False):
         """Full sweeps (there and back) until the energies of three subsequent
         sweeps agree within sweep_tol (the paper's stopping rule, 1e-5 Ha).
         E_s is the lowest energy met in sweep s, eps_s its largest truncation
         error.  Returns a dict with the per-sweep records, whether the rule was
         met, and the final window vector.  log (optional) receives one line
-        per sweep."""
+        per sweep.  refine: residual refinement in every window's eigensolver
+        (see davidson)."""
         from .extrapolate import sweep_converged
         sweeps = []
         cur = psi
         while len(sweeps) < max_sweeps:
-            halves, cur = self._half_sweeps(cur, 2, max_bond_dim, tol, ladder, None)
+            halves, cur = self._half_sweeps(cur, 2, max_bond_dim, tol, ladder, None, refine)
             sweeps.append({"min_energy": min(h["min_energy"] for h in halves),
                            "max_trunc": max(h["max_trunc"] for h in halves),
                            "davidson_s": sum(h["davidson_s"] for h in halves),

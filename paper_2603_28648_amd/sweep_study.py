@@ -23,7 +23,10 @@ CONFIGS = {
     "cas10_10": (10, 10, 0, 10, 1010),
     "cas8_8": (8, 8, 0, 8, 1008),
 }
-LADDERS = {"fp64": (("fp64", None),), "mixed": (("bf16x3", 1e-4), ("fp64", None))}
+# name: (ladder, residual refinement in the FP64 stage)
+LADDERS = {"fp64": ((("fp64", None),), False),
+           "mixed": ((("bf16x3", 1e-4), ("fp64", None)), False),
+           "refined": ((("bf16x3", 1e-4), ("fp64", None)), True)}
 
 
 def main():
@@ -62,8 +65,9 @@ def main():
             log(f"[sweeps] D={D} {msg}")
 
         t0 = time.perf_counter()
+        ladder, refine = LADDERS[args.ladder]
         r = ctx.sweep_to_convergence(psi, D, sweep_tol=args.sweep_tol, max_sweeps=args.max_sweeps,
-                                     tol=args.tol, ladder=LADDERS[args.ladder], log=sweep_log)
+                                     tol=args.tol, ladder=ladder, log=sweep_log, refine=refine)
         wall = time.perf_counter() - t0
         sw = r["sweeps"]
         rec = {"bond_dim": D, "sweeps": len(sw), "converged": r["converged"], "energy": r["energy"],
