@@ -40,3 +40,19 @@ def test_sweeps_at_d64_are_variational_and_monotone(ctx):
     assert E[-1] >= e_fci - 1e-10
     assert all(E[k + 1] <= E[k] + 1e-9 for k in range(len(E) - 1))
     assert E[-1] - e_fci < 5e-3
+
+
+def test_refined_sweeps_reach_fci_at_complete_bond_dimension(ctx):
+    """Sweeps whose window solves run split-BF16x3 and then residual
+    refinement (FP64 residuals, corrections on split-BF16x3) reach full CI."""
+    import torch
+    from oracle.fock import fci
+    print("sweeps K=8 D=256, split-BF16x3 + refinement, vs FCI", flush=True)
+    h, eri = make_integrals(8, 8)
+    m = make_mps(8, 8, 0, 256, 0, 1008)
+    ctx.build_ops(0, h=h, eri=eri, n_elec=8, two_sz=0, mps_arrays=mps_arrays(m))
+    psi = torch.from_numpy(pack_psi(m.bonds, 0, m.psi)).cuda()
+    E, eps, _ = ctx.sweep(psi, 3, 256, tol=1e-8, ladder=(("bf16x3", 1e-4), ("fp64", None)), refine=True)
+    e_fci = fci(8, 8, 0, h, eri)[0][0]
+    print(f"  E per half-sweep {[round(e, 12) for e in E]} FCI {e_fci:.12f}", flush=True)
+    assert abs(E[-1] - e_fci) < 1e-9
