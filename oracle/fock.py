@@ -25,6 +25,11 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  Plain definitions:
   gamma and Gamma / 2 are the derivatives of <bra|H|ket> with respect to the
   integral entries (each entry an independent input).
 
+* Total spin: s_squared(space, v) = <S^2> from S_+ and S_z (definition in
+  its docstring).  With the spin-summed 2-RDM above, any state of fixed N
+  has <S^2> = -N (N - 4) / 4 - 1/2 sum_pq Gamma_pqqp (tests pin this
+  identity on random vectors).
+
 Pins: tests/test_oracle_fock.py (closed forms: g=0 orbital sums, two-site
 Hubbard, K=1; [H,N]=[H,Sz]=0 on the full Fock space; the raw spin-orbital
 Hamiltonian on tiny spaces); tests/test_oracle_rdm.py (single-determinant
@@ -207,6 +212,29 @@ def fci(n_orb, n_elec, two_sz, h, eri, nroots=1, dense_limit=6000):
                       v0=rng.normal(size=space.dim), maxiter=5000)
     o = np.argsort(w)
     return w[o][:nroots], v[:, o][:, :nroots], space
+
+
+def s_squared(space, vec):
+    """<S^2> of a vector of the (N, 2Sz) sector `space`, from the spin-orbital
+    definition S^2 = S_- S_+ + S_z (S_z + 1), S_+ = sum_i a+_{i up} a_{i dn},
+    S_- = S_+^T: S_+ maps the sector into (N, 2Sz + 2), and
+    <S_- S_+> = |S_+ v|^2.  Normalised by |v|^2."""
+    vec = np.asarray(vec, dtype=np.float64)
+    n_elec = int(_popcount(space.dets[:1])[0])
+    mup = np.int64(sum(1 << (2 * i) for i in range(space.K)))
+    d0 = space.dets[:1]
+    two_sz = int(_popcount(d0 & mup)[0] - _popcount(d0 & (mup << np.int64(1)))[0])
+    sz = two_sz / 2.0
+    norm2 = float(vec @ vec)
+    val = sz * (sz + 1.0) * norm2
+    try:
+        target = DetSpace.sector(space.K, n_elec, two_sz + 2)
+    except ValueError:
+        return val / norm2
+    w = np.zeros(target.dim)
+    for i in range(space.K):
+        w += space.string_matrix([(2 * i, True), (2 * i + 1, False)], target) @ vec
+    return (val + float(w @ w)) / norm2
 
 
 def rdm12(space, bra, ket):

@@ -109,6 +109,16 @@ def test_backward_equals_fci_rdms_with_exact_bonds(ctx):
     print(f"  max|gamma - gamma_FCI| = {err_g:.2e}, max|Gamma - Gamma_FCI| = {err_G:.2e}", flush=True)
     assert err_g < 1e-8
     assert err_G < 1e-8
+    # total spin of the GPU state from its 2-RDM: <S^2> = -N(N-4)/4 - 1/2 sum_pq Gamma_pqqp,
+    # against the oracle's S_- S_+ + S_z(S_z + 1) on the FCI vector; an eigenstate, S(S+1)
+    from oracle.fock import s_squared
+    N = 10
+    s2 = -N * (N - 4) / 4 - 0.5 * float(np.einsum("pqqp->", 2 * deri))
+    s2_fci = s_squared(space, v[:, 0])
+    S = (-1 + np.sqrt(1 + 4 * max(s2, 0.0))) / 2
+    print(f"  <S^2> from the GPU 2-RDM {s2:.3e}, FCI {s2_fci:.3e}, S = {S:.6f}", flush=True)
+    assert abs(s2 - s2_fci) < 1e-7
+    assert abs(S - round(S)) < 1e-6
 
 
 def _c4(ctx):
