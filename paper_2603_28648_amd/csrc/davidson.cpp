@@ -2,7 +2,7 @@
 // the diagonal preconditioner and a precision ladder for the sigma products.
 //
 // Vectors live on the device in FP64; the subspace matrices (k <= 64) are
-// diagonalised on the device in FP64 (rocSOLVER dsyevd), and their
+// diagonalised on the device in FP64 (rocSOLVER dsyevj), and their
 // eigenvectors are copied to the host, which picks the Ritz pair and the
 // restart combinations.  Each ladder stage
 // uses one sigma precision until the residual norm drops below the stage
@@ -154,15 +154,17 @@ int davidson(SigmaPlan& plan, double* psi, const DavidsonOpts& o, DavidsonResult
   DMRG_REQUIRE(rocblas_set_stream(solver.h, s) == rocblas_status_success, kErrHip,
                "davidson: rocblas_set_stream failed");
   DevBuf eigA((size_t)kmax * kmax * sizeof(double)), eigD(kmax * sizeof(double)),
-      eigE(kmax * sizeof(double)), eigInfo(sizeof(rocblas_int));
+      eigRes(sizeof(double)), eigInfo(2 * sizeof(rocblas_int));
   std::vector<double> colmaj((size_t)kmax * kmax);
   auto subspace_eigh = [&](int k, const std::vector<double>& Gk, std::vector<double>& ev_,
                            std::vector<double>& Y_) {
     DMRG_HIP(hipMemcpyAsync(eigA.p, Gk.data(), (size_t)k * k * sizeof(double), hipMemcpyHostToDevice, s));
-    DMRG_REQUIRE(rocsolver_dsyevd(solver.h, rocblas_evect_original, rocblas_fill_upper, k, eigA.as<double>(),
-                                  k, eigD.as<double>(), eigE.as<double>(),
+    // cyclic Jacobi (one small-matrix kernel); tolerance: machine precision
+    DMRG_REQUIRE(rocsolver_dsyevj(solver.h, rocblas_esort_ascending, rocblas_evect_original, rocblas_fill_upper,
+                                  k, eigA.as<double>(), k, 0.0, eigRes.as<double>(), 100,
+                                  eigInfo.as<rocblas_int>() + 1, eigD.as<double>(),
                                   eigInfo.as<rocblas_int>()) == rocblas_status_success,
-                 kErrHip, "davidson: rocsolver_dsyevd failed");
+                 kErrHip, "davidson: rocsolver_dsyevj failed");
     ev_.resize(k);
     rocblas_int info = 0;
     DMRG_HIP(hipMemcpyAsync(ev_.data(), eigD.p, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, s));
