@@ -9,7 +9,9 @@
 // threshold, reaches the floor that precision allows, or stalls; the
 // subspace is then restarted from the current Ritz vector with sigma
 // recomputed in the next precision.  The last stage is FP64, and the returned
-// energy is the FP64 Rayleigh quotient.
+// energy is the FP64 Rayleigh quotient.  With residual refinement, the FP64
+// stage takes its correction vectors from inexact Jacobi-Davidson solves on
+// the previous stage's precision (below).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
