@@ -9,14 +9,17 @@ generators in ``synthetic`` feed both.
 Modules
 -------
 fock        determinant (Fock) space, spin-orbital operators, the
-            Hamiltonian of the Method section, FCI (plain definitions).
+            Hamiltonian of the Method section, FCI, transition 1-/2-RDMs and
+            the total spin <S^2> (plain definitions).
 projection  the MPS of eq. (1) contracted into Fock vectors, the
             effective Hamiltonian P^T H P and its action (plain definition).
-blocksparse renormalised block operators and the normal/complementary
-            sigma (the standard ab initio DMRG algorithm, written out).
-dmrg        two-site sweeps, truncation, Davidson (standard algorithm).
-rdm         one- and two-particle reduced density matrices.
+blocksparse renormalised block operators, the normal/complementary sigma and
+            diag(H_eff) (the standard ab initio DMRG algorithm, written out).
+truncation  the two-site truncation (per-sector SVD, global selection of the
+            D largest weights, truncation error) and the window move.
+orbital     generalised Fock matrix and orbital gradient from the RDMs.
 
-Parity status of every function is listed in its docstring; all functions
-here are pinned by tests under tests/ (no function is "parity unpinned").
+Every function is pinned by tests under tests/ (test_oracle_*.py) against
+closed forms, brute force or the plain definitions; the pins are listed in
+each module's docstring.
 """

@@ -767,3 +767,35 @@ class BlockSparseSigma:
         tmpl = {k: v.shape for k, v in psi.items()}
         return self.from_matrix(self.apply_matrix(self.to_matrix(psi)), tmpl)
 
+    def diagonal(self, template):
+        """diag(H_eff) in psi blocks (template: {(l, n1, n2): shape}).
+
+        A product X_L (x) X_R of the partition reaches a diagonal element
+        <l r|X_L X_R|l r> only if both factors keep their quantum numbers
+        (dq = 0, hence even parity and no Jordan-Wigner sign); the element is
+        then X_L[l, l] X_R[r, r].  Summed over the terms of the partition.
+        Pin: equals the diagonal of the dense P^T H P (projection.py) at
+        small sizes (tests/test_oracle_blocksparse.py)."""
+        EL, ER = self.EL, self.ER
+        out = self.to_matrix({k: np.zeros(shape) for k, shape in template.items()})
+        for (coef, XL, XR) in self.terms:
+            if (XL is not None and XL.dq != (0, 0)) or (XR is not None and XR.dq != (0, 0)):
+                continue
+            for kl, (kr, D) in out.items():
+                if XL is None:
+                    dl = np.ones(EL.dim[kl])
+                else:
+                    blk = XL.blocks.get((kl, kl))
+                    if blk is None:
+                        continue
+                    dl = np.diag(blk)
+                if XR is None:
+                    dr = np.ones(ER.dim[kr])
+                else:
+                    blk = XR.blocks.get((kr, kr))
+                    if blk is None:
+                        continue
+                    dr = np.diag(blk)
+                D += coef * np.outer(dl, dr)
+        return self.from_matrix(out, template)
+

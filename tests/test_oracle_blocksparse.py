@@ -51,3 +51,17 @@ def test_planted_sign_error_is_caught():
     bad = [(c, XL, Even(XR) if XR is not None else None) for (c, XL, XR) in flipped]
     got = b.from_matrix(b.apply_matrix(b.to_matrix(m.psi), bad), {k: v.shape for k, v in m.psi.items()})
     assert _rel(got, ref) > 1e-3
+
+
+@pytest.mark.parametrize("K,N,tsz,D,i", [(4, 4, 0, 100, 1), (5, 4, -2, 12, 3), (6, 6, 2, 12, 3),
+                                         (6, 5, 1, 10, 0), (7, 7, 1, 30, 2)])
+def test_diagonal_equals_dense_projection(K, N, tsz, D, i):
+    """diag(H_eff) of the partition equals the diagonal of the dense P^T H P."""
+    from oracle.projection import psi_template
+    h, eri = make_integrals(K, 11 + K)
+    m = make_mps(K, N, tsz, D, i, 5 + i)
+    dense, keys = ProjectedHamiltonian(m, h, eri).dense()
+    tmpl = psi_template(m)
+    got = BlockSparseSigma(m, h, eri).diagonal(tmpl)
+    flat = np.concatenate([got[k].ravel() for k in keys])
+    assert np.max(np.abs(flat - np.diag(dense))) < 1e-12 * np.max(np.abs(np.diag(dense)))
