@@ -2,7 +2,7 @@
 
     python bench.py [--steps K] [--warmup W] [--config cas54_36|cas54_36_sz2|cas22_22]
                     [--precision bf16x3|bf16|fp64] [--fp64-steps K64] [--dav-iters I]
-                    [--no-cpu-baseline]
+                    [--dav-solve 0|1|2|3] [--no-cpu-baseline]
 
 Workload (default): CAS(54,36)-shaped active space (36 orbitals, 54
 electrons, 2Sz = 0), bond dimension D = 4096, middle window (17, 18),
@@ -11,11 +11,16 @@ Operators are built once (dmrg_build_ops, untimed); a timed step is one
 sigma = H_eff psi on the resident psi in the mixed precision (split-BF16x3
 MFMA, block Hamiltonians in FP64) unless --precision says otherwise.  The
 JSON line reports algorithmic sigma TFLOP/s; beside it the FP64 sigma of the
-same psi (time, relative difference, Rayleigh-quotient difference), the
-Davidson step time with the mixed ladder, the roofline of the dominant
-grouped-GEMM kernel from HIP events the library records around each launch
-on its stream, and the CPU oracle timed on a bounded sample of the same
-contraction on the host cores.
+same psi (time, relative difference, Rayleigh-quotient difference, its own
+roofline), the Ozaki-scheme sigma (FP64 emulated on INT8, the paper's
+47-bit setting) with its roofline, the Davidson step time with the mixed
+ladder, a Davidson solve to the paper's eigensolver tolerance (residual
+1e-6 with FP64 sigma products) with the mixed ladder and residual
+refinement (time to solution, FP64 residual and energy; --dav-solve 1 adds
+the ladder alone and FP64 alone for the energy difference), the roofline of
+the dominant grouped-GEMM kernel from HIP events the library records around
+each launch on its stream, and the CPU oracle timed on a bounded sample of
+the same contraction on the host cores.
 """
 import argparse
 import json
@@ -65,15 +70,23 @@ def profiled_traffic(kernel_src, config):
     return float(m_tr.group(1)), int(m_ln.group(1))
 
 
-def cpu_baseline(m, n_terms=6, seed=0):
-    """Oracle contraction timed on a sample of its partition terms.
+def cpu_baseline(m, reps=2, seed=0):
+    """The oracle's sigma time on this window, from a stratified sample of
+    its partition terms.
 
-    The oracle applies each term as dense products of enlarged-block
-    operators (block + one site, in its enlarged sectors).  The sample uses
-    its own code (BlockSparseSigma.apply_matrix) on the real enlarged bases
-    of this window with random operators of the dominant kind (two-index
-    operators with zero quantum-number change on both sides); the time per
-    term is scaled by the oracle's term count of this window.
+    The oracle applies each partition term O_L (x) O_R as dense products of
+    enlarged-block operators (BlockSparseSigma.apply_matrix).  Its terms fall
+    into 13 classes by the quantum-number change of O_L (O_R carries the
+    opposite): H_L (x) 1 and 1 (x) H_R, a+_p S_p / a_p S_p^+ and T_m a_m /
+    T_m^+ a+_m (change (+-1, +-1)), A_pq P_pq and its conjugate ((+-2, 0),
+    (+-2, +-2)), B_pq Q_pq ((0, 0), (0, +-2)).  The oracle cannot build this
+    window's operators in bounded time, so each class is timed with the
+    oracle's own contraction on the real enlarged sectors of the window and
+    random operators filling every block the class allows (the values do not
+    change the work), and the time per class is multiplied by the number of
+    terms of that class in the window (counted from the spin-orbitals on each
+    side).  Returns (modelled seconds per sigma, seconds timed, classes,
+    terms).
     """
     from oracle import blocksparse as bs
     rng = np.random.default_rng(seed)
@@ -87,17 +100,40 @@ def cpu_baseline(m, n_terms=6, seed=0):
     obj.mps, obj.EL, obj.ER, obj.q_tot = m, EL, ER, q_tot
     Psi = obj.to_matrix(m.psi)
 
-    def rand_op(E):
-        return bs.Op((0, 0), {(k, k): rng.normal(size=(E.dim[k], E.dim[k])) for k in range(len(E.qn))})
-    XL, XR = rand_op(EL), rand_op(ER)
-    M = 2 * (i + 1)
-    n_all = 2 + 4 * M + M * (M - 1) + M * M  # partition terms of this window
-    obj.apply_matrix(Psi, [(1.0, XL, XR)])  # warm-up (BLAS threads)
+    def rand_op(E, dq):
+        blocks = {}
+        for kc, qc in enumerate(E.qn):
+            kr = E.idx.get((qc[0] + dq[0], qc[1] + dq[1]))
+            if kr is not None:
+                blocks[(kr, kc)] = rng.normal(size=(E.dim[kr], E.dim[kc]))
+        return bs.Op(dq, blocks)
+
+    ML, MR = 2 * (i + 1), 2 * (K - i - 1)  # spin-orbitals left / right of the cut
+    hl, hr = ML // 2, MR // 2             # per spin
+    counts = {(0, 0): 2 * hl * hl, (0, 2): hl * hl, (0, -2): hl * hl,
+              (2, 0): hl * hl, (-2, 0): hl * hl,
+              (2, 2): hl * (hl - 1) // 2, (2, -2): hl * (hl - 1) // 2,
+              (-2, 2): hl * (hl - 1) // 2, (-2, -2): hl * (hl - 1) // 2}
+    for d in ((1, 1), (1, -1), (-1, 1), (-1, -1)):
+        counts[d] = hl + hr  # a+_p S_p (or conjugate) for p left, T_m a_m for m right
+    t_model, t_spent = 0.0, 0.0
+    for dq, cnt in counts.items():
+        XL = rand_op(EL, dq)
+        XR = rand_op(ER, (-dq[0], -dq[1]))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            obj.apply_matrix(Psi, [(1.0, XL, XR)])
+        dt = (time.perf_counter() - t0) / reps
+        t_spent += dt * reps
+        t_model += dt * cnt
+    # the two block Hamiltonians: one-sided products
+    HL, HR = rand_op(EL, (0, 0)), rand_op(ER, (0, 0))
     t0 = time.perf_counter()
-    for _ in range(n_terms):
-        obj.apply_matrix(Psi, [(1.0, XL, XR)])
-    dt = (time.perf_counter() - t0) / n_terms
-    return dt * n_all, n_terms, n_all, dt
+    obj.apply_matrix(Psi, [(1.0, HL, None), (1.0, None, HR)])
+    dt = time.perf_counter() - t0
+    t_spent += dt
+    t_model += dt
+    return t_model, t_spent, len(counts) + 1, sum(counts.values()) + 2
 
 
 def main():
@@ -114,7 +150,7 @@ def main():
                     help="plain BF16 sigma steps timed beside the headline (0: skip)")
     ap.add_argument("--dav-iters", type=int, default=4,
                     help="Davidson iterations timed with the mixed ladder (0: skip)")
-    ap.add_argument("--dav-solve", type=int, default=0,
+    ap.add_argument("--dav-solve", type=int, default=3,
                     help="1: also solve to residual 1e-6 with the mixed ladder, with the mixed ladder "
                          "and residual refinement, and with FP64 alone (time-to-solution and energy "
                          "differences; minutes at CAS(54,36)); 2: the mixed ladder only; 3: the "
@@ -124,7 +160,8 @@ def main():
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch each sigma kernel by kernel instead of replaying a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-terms", type=int, default=30)
+    ap.add_argument("--cpu-reps", type=int, default=20,
+                    help="repeats of each term class in the CPU-oracle sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of MB megabytes, 3 times "
                          "(reference for the HBM byte counters), then exit")
@@ -172,6 +209,18 @@ def main():
     ref = torch.empty_like(psi)
     torch.cuda.synchronize()
 
+    def kernel_roofline(kt, kname, peak, unit, hw_per_flop):
+        """Achieved rate of the main-stage grouped-GEMM launches of the timed
+        calls: algorithmic FLOPs per launch (times hw_per_flop hardware
+        operations per FLOP) over the average launch time from the library's
+        HIP events on its stream."""
+        n = kt["launches_stage1"] + kt["launches_stage2"]
+        ms_k = (kt["ms_stage1"] + kt["ms_stage2"]) / max(1, n)
+        fl = (kt["flops_stage1"] + kt["flops_stage2"]) * kt["calls"] / max(1, n)
+        ach = hw_per_flop * fl / (ms_k * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                "kernel": kname, "launches_per_step": n / max(1, kt["calls"]), "avg_launch_ms": ms_k}
+
     def timed_sigma(prec, steps, warmup, target, kernel_timing):
         """Event times of `steps` sigma calls on the library stream; with
         kernel_timing, also the library's per-launch kernel times over the same
@@ -203,9 +252,12 @@ def main():
     stream.synchronize()
     ctx.sigma_graphs(not args.no_graphs)
     if args.fp64_steps > 0 and args.precision != "fp64":
-        t64, _, _ = timed_sigma("fp64", args.fp64_steps, 0, ref, False)
+        t64, kt64, _ = timed_sigma("fp64", args.fp64_steps, 0, ref, True)
         fp64 = {"ms": float(np.median(t64)), "tflops": info["flops"] / (np.median(t64) * 1e-3) / 1e12}
-        log(f"[bench] sigma fp64: median {fp64['ms']:.2f} ms ({fp64['tflops']:.2f} TFLOP/s)")
+        fp64["frac_of_fp64_peak"] = fp64["tflops"] / PEAK_TFLOPS["fp64"]
+        fp64["roofline"] = kernel_roofline(kt64, "k_gemm_f64", PEAK_TFLOPS["fp64"], "TFLOP/s", 1.0)
+        log(f"[bench] sigma fp64: median {fp64['ms']:.2f} ms ({fp64['tflops']:.2f} TFLOP/s); "
+            f"k_gemm_f64 {fp64['roofline']['achieved']:.1f} TFLOP/s per launch")
     times, _, t_wall = timed_sigma(args.precision, args.steps, args.warmup, out, False)
     ms = float(np.median(times))
     # per-kernel times for the roofline: a few more steps with the timing hook
@@ -277,7 +329,9 @@ def main():
                          "converged": bool(r["converged"])}
             log(f"[bench] davidson solve {name}: {res[name]['time_s']:.1f} s, {r['iterations']} iterations, "
                 f"sigma calls {r['n_sigma']}, E={r['energy']:.10f}, residual {r['residual']:.1e}")
-        solve = {"tol": 1e-6, "ladder": [list(x) for x in ladder], **res}
+        solve = {"tol": 1e-6, "ladder": [list(x) for x in ladder],
+                 "note": "residual = ||H u - E u||_2 with FP64 sigma, |u| = 1 (the paper's eigensolver "
+                         "tolerance 1e-6); energy = FP64 Rayleigh quotient", **res}
         if "fp64" in res:
             for name in ("mixed", "refined"):
                 solve[f"energy_diff_{name}"] = res[name]["energy"] - res["fp64"]["energy"]
@@ -305,23 +359,29 @@ def main():
                  "stage2_ms": kto["ms_stage2"] / max(1, kto["calls"]),
                  "slicing_ms": kto["ms_convert"] / max(1, kto["calls"]),
                  "pinned_fp64_ms": kto["ms_pinned"] / max(1, kto["calls"]),
-                 "int8_tops": int8_tops, "int8_peak_tops": 5000.0, "int8_frac": int8_tops / 5000.0}
+                 "int8_tops": int8_tops, "int8_peak_tops": 5000.0, "int8_frac": int8_tops / 5000.0,
+                 "roofline": kernel_roofline(kto, "k_gemm_oz", 5000.0, "TOP/s (INT8)",
+                                             info_oz["hw_flops"] / info["flops"])}
         log(f"[bench] sigma ozaki ({kap} slices, {8 * kap - 1} bits): median {ms_oz:.1f} ms "
             f"({ozaki['tflops']:.1f} TFLOP/s FP64-equivalent), stage1 {ozaki['stage1_ms']:.1f} + stage2 "
             f"{ozaki['stage2_ms']:.1f} + slicing {ozaki['slicing_ms']:.1f} + pinned {ozaki['pinned_fp64_ms']:.1f} ms; "
             f"INT8 {int8_tops:.0f} TOP/s; |dsigma|/|sigma| = {rel_oz:.2e}")
     cpu = None
     if not args.no_cpu_baseline:
-        t_cpu, n_s, n_all, per = cpu_baseline(m, args.cpu_terms)
+        t_cpu, t_spent, n_cls, n_terms = cpu_baseline(m, args.cpu_reps)
         cores = len(os.sched_getaffinity(0))
         threads = int(os.environ.get("OMP_NUM_THREADS", cores))
         cpu = {"value": info["flops"] / t_cpu / 1e12, "unit": "TFLOP/s", "cores": min(cores, threads),
                "kind": "oracle",
-               "sample": f"oracle block-sparse term contraction (dense enlarged-block products) on "
-                         f"{n_s} of the window's {n_all} partition terms at the real CAS(54,36) "
-                         f"D={D} enlarged sectors, {per:.2f} s/term scaled to all terms; FLOPs "
-                         f"counted as the library's algorithmic sigma FLOPs"}
-        log(f"[bench] cpu oracle: {per:.2f} s/term -> {t_cpu:.0f} s/sigma")
+               "sample": f"the oracle's block-sparse contraction (BlockSparseSigma.apply_matrix, FP64 "
+                         f"NumPy) timed on the real enlarged sectors of this {args.config} window for "
+                         f"each of its {n_cls} term classes ({args.cpu_reps} repeats, {t_spent:.1f} s "
+                         f"timed), with random operators filling every block of the class",
+               "model": f"modelled sigma time {t_cpu:.0f} s = sum over classes of the timed time per "
+                        f"term x the class's term count ({n_terms} terms); value = the library's "
+                        f"algorithmic sigma FLOPs / that time",
+               "sigma_s_modelled": t_cpu}
+        log(f"[bench] cpu oracle: {t_spent:.1f} s timed over {n_cls} classes -> {t_cpu:.0f} s/sigma modelled")
     peak = PEAK_TFLOPS[args.precision]
     traffic = None
     if args.precision != "fp64" and args.config == "cas54_36":
@@ -347,6 +407,8 @@ def main():
         "config": {"workload": f"{args.config}: K={K} N={N} 2Sz={tsz} D={D} window=({i},{i + 1})",
                    "psi_size": m.psi_size(), "sigma_flops": info["flops"],
                    "sigma_flops_stages": [info["flops_stage1"], info["flops_stage2"]],
+                   "sigma_flops_per_term": info["flops_terms"],
+                   "stage1_flops_consumed_frac": info["flops_stage1_used"] / max(1.0, info["flops_stage1"]),
                    "pairs": info["n_pairs"], "precision": args.precision,
                    "build_ops_s": round(t_build, 2), "wall_s_timed": round(t_wall, 3),
                    "rayleigh": e_mix, "rayleigh_fp64": e_ref, "rayleigh_diff": e_mix - e_ref,

@@ -146,6 +146,12 @@ typedef struct {
    * order (1: sorted by operand) */
   int32_t bf_config_stage1, bf_config_stage2;
   double tune_ms;        /* time the autotuner took (0 if it did not run) */
+  double flops_terms;    /* the per-term count: sum over (Hamiltonian term, psi block) of the
+                            cheaper association order, min(2m'mn + 2m'nn', 2mnn' + 2m'mn') for
+                            O_L (m' x m) psi (m x n) O_R^T (n x n'); beside `flops`, which counts
+                            the GEMMs issued (stage 1 is shared by every term with the same right
+                            operator and multiplies whole psi sectors) */
+  double flops_stage1_used; /* stage-1 FLOPs of the rows that stage 2 reads */
 } dmrg_sigma_info;
 dmrg_status dmrg_sigma_get_info(dmrg_ctx ctx, int32_t precision, dmrg_sigma_info* out);
 
@@ -225,7 +231,7 @@ dmrg_status dmrg_davidson(dmrg_ctx ctx, double* psi_inout, const dmrg_davidson_o
 /* Reverse mode of the sigma with respect to the integrals.  For window
  * vectors psi and sigma_bar (device, psi layout of the current window;
  * sigma_bar NULL means psi) and the current MPS, f = <sigma_bar, H_eff psi>
- * is linear in the integrals of the Hamiltonian (Model section: the ab initio
+ * is linear in the integrals of the Hamiltonian (Method section: the ab initio
  * Hamiltonian with one- and two-electron integrals); its gradient is written
  * to dh (K*K) and deri (K^4), device pointers, same index order as the
  * integrals, overwritten:
@@ -276,6 +282,54 @@ dmrg_status dmrg_truncate(dmrg_ctx ctx, const double* psi, int32_t direction, in
 /* Copies the current window's guess left by dmrg_truncate (device pointer of
  * length dmrg_psi_size). */
 dmrg_status dmrg_get_psi(dmrg_ctx ctx, double* out);
+
+/* Checks a problem and (optionally, mps may be NULL) an MPS layout on the
+ * host, without a context or a device: the ranges and parity of the active
+ * space (N electrons in K orbitals, 2Sz), finite integrals, h symmetric and
+ * (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq) to 1e-10 of the largest entry (the
+ * real-orbital Hamiltonian of the Method section), and for the MPS: K sites,
+ * a window inside the chain, bond_offsets[0] = 0, every bond non-empty with
+ * sorted unique sectors and positive dimensions, bond 0 = (0,0) and
+ * bond K = (N, 2Sz) of dimension 1, and a non-NULL tensor with at least one
+ * allowed block for every site outside the window.  dmrg_build_ops applies
+ * the same checks.  Returns DMRG_ERR_INVALID_ARG or DMRG_ERR_SHAPE with the
+ * message in dmrg_last_error(NULL). */
+dmrg_status dmrg_validate(const dmrg_problem* problem, const dmrg_mps* mps);
+
+/* The sectors of bond `bond` (0..K) of the context's current MPS, e.g. the
+ * middle bond written by dmrg_truncate.  n_sectors receives the count; the
+ * three arrays (host, capacity entries each) receive (N, 2Sz, dim) in
+ * ascending order when non-NULL (all three or none). */
+dmrg_status dmrg_get_bond(dmrg_ctx ctx, int32_t bond, int32_t capacity, int32_t* n_sectors,
+                          int32_t* sector_n, int32_t* sector_2sz, int32_t* sector_dim);
+
+/* The MPS site tensor `site` of the context (the updated site out of a
+ * two-site step: after dmrg_truncate with direction +1 the new left-canonical
+ * tensor of the old window's left site, with -1 the new right-canonical tensor
+ * of its right site; the A of eq. (1) in the layout of dmrg_mps.site_data:
+ * blocks (l, n) -> r ascending by l then n, each d_l x d_r row-major, with
+ * the bonds of dmrg_get_bond).  size receives the number of doubles; out
+ * (host, capacity doubles) receives the tensor when non-NULL.  The window's
+ * two sites are held in psi and are refused (DMRG_ERR_STATE).  Synchronises
+ * the context stream. */
+dmrg_status dmrg_get_site(dmrg_ctx ctx, int32_t site, int64_t capacity, double* out, int64_t* size);
+
+/* Energy functional of a window vector (Method section: the energy of the
+ * MPS of eq. (1) with psi at the current window):
+ *   energy = psi^T H_eff psi + e_core psi^T psi,   norm2 = psi^T psi
+ * with sigma = H_eff psi in the given precision and both dot products in
+ * FP64 on the device (for normalised psi, the energy).  psi, sigma_out and
+ * grad_psi are device pointers of dmrg_psi_size doubles; sigma_out (may be
+ * NULL) receives sigma, grad_psi (may be NULL) the gradient
+ * d energy / d psi = 2 (sigma + e_core psi).  h and eri (host, K*K and K^4,
+ * both or neither) are compared with the integrals the operators were built
+ * from: a difference above 1e-13 of the largest entry is DMRG_ERR_INVALID_ARG,
+ * so a caller cannot take the energy of one Hamiltonian with the operators of
+ * another.  energy_out and norm2_out (may be NULL) are host pointers;
+ * synchronises the context stream. */
+dmrg_status dmrg_energy(dmrg_ctx ctx, const double* h, const double* eri, const double* psi,
+                        int32_t precision, double* sigma_out, double* grad_psi, double* energy_out,
+                        double* norm2_out);
 
 /* Diagnostic: copies diag(H_eff) of the current window (the Davidson
  * preconditioner; psi layout, device pointer, length dmrg_psi_size). */

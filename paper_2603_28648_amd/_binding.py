@@ -51,7 +51,8 @@ class SigmaInfo(ctypes.Structure):
                 ("operator_bytes", ctypes.c_int64), ("n_chunks", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("flops_stage1", ctypes.c_double),
                 ("flops_stage2", ctypes.c_double), ("bf_config_stage1", ctypes.c_int32),
-                ("bf_config_stage2", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
+                ("bf_config_stage2", ctypes.c_int32), ("tune_ms", ctypes.c_double),
+                ("flops_terms", ctypes.c_double), ("flops_stage1_used", ctypes.c_double)]
 
 
 class DavidsonOpts(ctypes.Structure):
@@ -102,6 +103,16 @@ EXPORTS = {
     "dmrg_sigma_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
     "dmrg_debug_diag": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dmrg_validate": (ctypes.c_int32, [ctypes.POINTER(Problem), ctypes.POINTER(Mps)]),
+    "dmrg_get_bond": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "dmrg_get_site": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    "dmrg_energy": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]),
     "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -140,6 +151,43 @@ def _dev_ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _problem(h, eri, n_elec, two_sz, e_core, keep):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    keep += [h, eri]
+    return Problem(h.shape[0], int(n_elec), int(two_sz), 0, float(e_core), _ptr(h), _ptr(eri))
+
+
+def _mps(mps_arrays, window, keep):
+    a = mps_arrays
+    K = len(a["sites"])
+    arrs = [np.ascontiguousarray(a[k], dtype=np.int32)
+            for k in ("bond_offsets", "sector_n", "sector_2sz", "sector_dim")]
+    keep += arrs
+    ptrs = (ctypes.POINTER(ctypes.c_double) * K)()
+    for b, s in enumerate(a["sites"]):
+        if s is not None:
+            s = np.ascontiguousarray(s, dtype=np.float64)
+            keep.append(s)
+            ptrs[b] = _ptr(s)
+    keep.append(ptrs)
+    return Mps(K, int(window), *[_ptr(x, ctypes.c_int32) for x in arrs],
+               ctypes.cast(ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))))
+
+
+def validate(h, eri, n_elec, two_sz, mps_arrays=None, window=0, e_core=0.0):
+    """Host-side check of a problem (and MPS layout) by dmrg_validate; needs no
+    GPU.  Raises DMRGError with the library's status and message."""
+    lib = load_library()
+    keep = []
+    prob = _problem(h, eri, n_elec, two_sz, e_core, keep)
+    mps = _mps(mps_arrays, window, keep) if mps_arrays is not None else None
+    st = lib.dmrg_validate(ctypes.byref(prob), ctypes.byref(mps) if mps is not None else None)
+    if st < 0:
+        raise DMRGError(st, lib.dmrg_last_error(None).decode())
+    return st
+
+
 class Context:
     """One library context on one GPU, ordered on torch's current stream."""
 
@@ -175,27 +223,11 @@ class Context:
         keep = []
         if h is not None:
             self._n_orb = int(np.asarray(h).shape[0])
-            h = np.ascontiguousarray(h, dtype=np.float64)
-            eri = np.ascontiguousarray(eri, dtype=np.float64)
-            keep += [h, eri]
             self._e_core = float(e_core)
-            prob = Problem(h.shape[0], int(n_elec), int(two_sz), 0, float(e_core), _ptr(h), _ptr(eri))
+            prob = _problem(h, eri, n_elec, two_sz, e_core, keep)
         mps = None
         if mps_arrays is not None:
-            a = mps_arrays
-            K = len(a["sites"])
-            arrs = [np.ascontiguousarray(a[k], dtype=np.int32)
-                    for k in ("bond_offsets", "sector_n", "sector_2sz", "sector_dim")]
-            keep += arrs
-            ptrs = (ctypes.POINTER(ctypes.c_double) * K)()
-            for b, s in enumerate(a["sites"]):
-                if s is not None:
-                    s = np.ascontiguousarray(s, dtype=np.float64)
-                    keep.append(s)
-                    ptrs[b] = _ptr(s)
-            keep.append(ptrs)
-            mps = Mps(K, int(site if window is None else window), *[_ptr(x, ctypes.c_int32) for x in arrs],
-                      ctypes.cast(ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))))
+            mps = _mps(mps_arrays, site if window is None else window, keep)
         st = self.lib.dmrg_build_ops(self.h, ctypes.byref(prob) if prob else None,
                                      ctypes.byref(mps) if mps else None, int(site), int(direction),
                                      int(precision_mask))
@@ -371,6 +403,45 @@ class Context:
         return {"sweeps": sweeps, "converged": converged, "energy": sweeps[-1]["min_energy"],
                 "max_trunc": sweeps[-1]["max_trunc"], "psi": cur}
 
+    def get_bond(self, bond):
+        """Sectors of a bond of the context's MPS: list of (N, 2Sz, dim)."""
+        n = ctypes.c_int32()
+        self._check(self.lib.dmrg_get_bond(self.h, int(bond), 0, ctypes.byref(n), None, None, None), self.h)
+        a = [np.zeros(max(1, n.value), dtype=np.int32) for _ in range(3)]
+        self._check(self.lib.dmrg_get_bond(self.h, int(bond), n.value, ctypes.byref(n),
+                                           *[_ptr(x, ctypes.c_int32) for x in a]), self.h)
+        return [(int(a[0][k]), int(a[1][k]), int(a[2][k])) for k in range(n.value)]
+
+    def get_site(self, site):
+        """The packed site tensor of a site outside the window (host float64
+        array in the dmrg_mps layout)."""
+        n = ctypes.c_int64()
+        self._check(self.lib.dmrg_get_site(self.h, int(site), 0, None, ctypes.byref(n)), self.h)
+        out = np.zeros(max(1, n.value), dtype=np.float64)
+        self._check(self.lib.dmrg_get_site(self.h, int(site), n.value, _ptr(out), ctypes.byref(n)), self.h)
+        return out[:n.value]
+
+    def energy(self, psi, precision="fp64", h=None, eri=None, sigma=None, grad=None):
+        """(psi^T H_eff psi + e_core psi^T psi, psi^T psi) from dmrg_energy;
+        sigma / grad (device tensors, optional) receive H_eff psi and
+        2 (sigma + e_core psi).  h / eri (optional) are checked against the
+        integrals the operators were built from."""
+        keep = []
+        hp = ep = None
+        if h is not None:
+            hh = np.ascontiguousarray(np.asarray(h, dtype=np.float64))
+            ee = np.ascontiguousarray(np.asarray(eri, dtype=np.float64))
+            keep += [hh, ee]
+            hp, ep = _ptr(hh), _ptr(ee)
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        e = ctypes.c_double()
+        nrm = ctypes.c_double()
+        self._check(self.lib.dmrg_energy(self.h, hp, ep, _dev_ptr(psi), p,
+                                         _dev_ptr(sigma) if sigma is not None else None,
+                                         _dev_ptr(grad) if grad is not None else None,
+                                         ctypes.byref(e), ctypes.byref(nrm)), self.h)
+        return e.value, nrm.value
+
     def debug_diag(self, out):
         self._check(self.lib.dmrg_debug_diag(self.h, _dev_ptr(out)), self.h)
         return out
@@ -399,10 +470,12 @@ class DMRGEnergy:
     torch.autograd.Function of the integrals and the window vector.
 
     ``DMRGEnergy.apply(h, eri, psi, ctx)``: ctx is a Context whose operators
-    were built from exactly these integrals for the window psi belongs to
-    (the MPS outside the window is held fixed).  The backward returns
-    (E_bar * gamma, E_bar * Gamma / 2, 2 E_bar * H_eff psi) from
-    dmrg_sigma_backward and the sigma.
+    were built from these integrals for the window psi belongs to (the MPS
+    outside the window is held fixed); dmrg_energy computes E and its psi
+    gradient and refuses integrals that differ from the built ones.  The
+    backward returns (E_bar * gamma, E_bar * Gamma / 2,
+    E_bar * 2 (H_eff psi + e_core psi)) from dmrg_sigma_backward and
+    dmrg_energy.
     """
 
     _fn = None
@@ -415,20 +488,19 @@ class DMRGEnergy:
             class _F(torch.autograd.Function):
                 @staticmethod
                 def forward(fctx, h, eri, psi, c):
-                    if tuple(h.shape) != (c._n_orb, c._n_orb):
-                        raise ValueError("h does not match the context's problem")
-                    sig = torch.empty_like(psi)
-                    c.sigma(psi.detach().contiguous(), sig)
-                    fctx.save_for_backward(psi, sig)
+                    p = psi.detach().contiguous()
+                    grad = torch.empty_like(p)
+                    e, _ = c.energy(p, h=h.detach().cpu().numpy(), eri=eri.detach().cpu().numpy(),
+                                    grad=grad)
+                    fctx.save_for_backward(p, grad)
                     fctx.c = c
-                    return torch.dot(psi, sig) + c._e_core * torch.dot(psi, psi)
+                    return torch.tensor(e, dtype=torch.float64, device=psi.device)
 
                 @staticmethod
                 def backward(fctx, gE):
-                    psi, sig = fctx.saved_tensors
-                    dh, deri = fctx.c.sigma_backward(psi.detach().contiguous())
-                    gpsi = 2.0 * gE * (sig + fctx.c._e_core * psi)
-                    return gE * dh, gE * deri, gpsi, None
+                    psi, grad = fctx.saved_tensors
+                    dh, deri = fctx.c.sigma_backward(psi)
+                    return gE * dh, gE * deri, gE * grad, None
 
             cls._fn = _F
         return cls._fn.apply(h, eri, psi, ctx)

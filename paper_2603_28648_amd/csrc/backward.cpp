@@ -618,13 +618,13 @@ void orbital_gradient(const Problem& P, const double* dh, const double* deri, do
   f.segs.push_back({dh, dH.p, K, K, K, kTransB, 1.0});
   f.segs.push_back({deri, dE.p, (int)K3, (int)K3, (int)K3, kTransB, 2.0});
   f.add_problem(F, K, K, K, 0, 2, 0);
-  launch_gemm_f64(f, desc, s);
+  launch_gemm_f64(f, s);
   // g = 2 F^T I - 2 F I
   GemmBatch g;
   g.segs.push_back({F, dI.p, K, K, K, kTransA, 2.0});
   g.segs.push_back({F, dI.p, K, K, K, 0, -2.0});
   g.add_problem(grad, K, K, K, 0, 2, 0);
-  launch_gemm_f64(g, desc, s);
+  launch_gemm_f64(g, s);
   DMRG_HIP(hipStreamSynchronize(s));
 }
 

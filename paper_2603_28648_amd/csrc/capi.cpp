@@ -2,6 +2,7 @@
 // host before any device work; exceptions never cross the ABI.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -97,37 +98,78 @@ dmrg_status dmrg_destroy(dmrg_ctx c) {
 
 const char* dmrg_last_error(dmrg_ctx c) { return c ? c->err.c_str() : g_err.c_str(); }
 
-static void load_problem(dmrg_ctx c, const dmrg_problem* p) {
+// Host-side checks of the active space and the integrals: ranges, parity,
+// and the symmetries the operator algebra relies on (h symmetric, (pq|rs)
+// with the 8-fold permutational symmetry of real orbitals), each to
+// 1e-10 of the largest entry.
+static void validate_problem(const dmrg_problem* p) {
+  DMRG_REQUIRE(p, kErrInvalidArg, "problem is NULL");
   DMRG_REQUIRE(p->h && p->eri, kErrInvalidArg, "problem: h and eri must be non-NULL");
   const int K = p->n_orb, N = p->n_elec, t = p->two_sz;
   DMRG_REQUIRE(K >= 2 && K <= 127, kErrInvalidArg, "problem: need 2 <= n_orb <= 127");
   DMRG_REQUIRE(N >= 0 && N <= 2 * K, kErrInvalidArg, "problem: need 0 <= n_elec <= 2*n_orb");
   DMRG_REQUIRE(((N - t) % 2) == 0, kErrInvalidArg, "problem: n_elec and two_sz must have equal parity");
   DMRG_REQUIRE(std::abs(t) <= std::min(N, 2 * K - N), kErrInvalidArg, "problem: |two_sz| too large");
+  DMRG_REQUIRE(std::isfinite(p->e_core), kErrInvalidArg, "problem: e_core is not finite");
+  const size_t K2 = (size_t)K * K;
+  double hmax = 0, gmax = 0;
+  for (size_t a = 0; a < K2; ++a) {
+    DMRG_REQUIRE(std::isfinite(p->h[a]), kErrInvalidArg, "problem: h has a non-finite entry");
+    hmax = std::max(hmax, std::fabs(p->h[a]));
+  }
+  for (size_t a = 0; a < K2 * K2; ++a) {
+    DMRG_REQUIRE(std::isfinite(p->eri[a]), kErrInvalidArg, "problem: eri has a non-finite entry");
+    gmax = std::max(gmax, std::fabs(p->eri[a]));
+  }
+  const double th = 1e-10 * std::max(1.0, hmax), tg = 1e-10 * std::max(1.0, gmax);
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < a; ++b)
+      DMRG_REQUIRE(std::fabs(p->h[(size_t)a * K + b] - p->h[(size_t)b * K + a]) <= th, kErrInvalidArg,
+                   "problem: h is not symmetric");
+  auto g = [&](int a, int b, int c, int d) { return p->eri[(((size_t)a * K + b) * K + c) * K + d]; };
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < K; ++b)
+      for (int c = 0; c < K; ++c)
+        for (int d = 0; d < K; ++d) {
+          const double x = g(a, b, c, d);
+          DMRG_REQUIRE(std::fabs(x - g(b, a, c, d)) <= tg && std::fabs(x - g(a, b, d, c)) <= tg &&
+                           std::fabs(x - g(c, d, a, b)) <= tg,
+                       kErrInvalidArg, "problem: eri lacks the 8-fold symmetry (pq|rs) = (qp|rs) = (pq|sr) = (rs|pq)");
+        }
+}
+
+static void load_problem(dmrg_ctx c, const dmrg_problem* p) {
+  validate_problem(p);
+  const int K = p->n_orb;
   c->P.K = K;
-  c->P.N = N;
-  c->P.tsz = t;
+  c->P.N = p->n_elec;
+  c->P.tsz = p->two_sz;
   c->P.e_core = p->e_core;
   c->P.h.assign(p->h, p->h + (size_t)K * K);
   c->P.eri.assign(p->eri, p->eri + (size_t)K * K * K * K);
   c->have_problem = true;
 }
 
-static void load_mps(dmrg_ctx c, const dmrg_mps* q) {
-  DMRG_REQUIRE(c->have_problem, kErrState, "mps: load a problem first");
-  const int K = c->P.K;
+// Host-side checks of the MPS layout against the active space (K sites,
+// sorted unique sectors, boundary bonds (0,0) and (N, 2Sz), positive
+// dimensions, a tensor for every site outside the window); returns the bonds
+// and, per site outside the window, the number of doubles of its tensor.
+static Mps parse_mps(int K, int N, int tsz, const dmrg_mps* q, std::vector<int64_t>& site_size) {
+  DMRG_REQUIRE(q, kErrInvalidArg, "mps is NULL");
   DMRG_REQUIRE(q->n_sites == K, kErrShape, "mps: n_sites differs from n_orb");
   DMRG_REQUIRE(q->bond_offsets && q->sector_n && q->sector_2sz && q->sector_dim && q->site_data,
                kErrInvalidArg, "mps: NULL array");
   DMRG_REQUIRE(q->window >= 0 && q->window <= K - 2, kErrInvalidArg, "mps: window out of range");
   Mps m;
   m.K = K;
-  m.N = c->P.N;
-  m.tsz = c->P.tsz;
+  m.N = N;
+  m.tsz = tsz;
   m.bonds.resize(K + 1);
+  DMRG_REQUIRE(q->bond_offsets[0] == 0, kErrShape, "mps: bond_offsets[0] must be 0");
   for (int b = 0; b <= K; ++b) {
     const int s0 = q->bond_offsets[b], s1 = q->bond_offsets[b + 1];
     DMRG_REQUIRE(s0 >= 0 && s1 >= s0, kErrShape, "mps: bond offsets must be non-decreasing");
+    DMRG_REQUIRE(s1 > s0, kErrShape, "mps: every bond needs at least one sector");
     Bond& B = m.bonds[b];
     for (int s = s0; s < s1; ++s) {
       QN x{q->sector_n[s], q->sector_2sz[s]};
@@ -140,13 +182,32 @@ static void load_mps(dmrg_ctx c, const dmrg_mps* q) {
   }
   DMRG_REQUIRE(m.bonds[0].size() == 1 && m.bonds[0].q[0] == (QN{0, 0}) && m.bonds[0].d[0] == 1,
                kErrShape, "mps: bond 0 must be (0,0) of dim 1");
-  DMRG_REQUIRE(m.bonds[K].size() == 1 && m.bonds[K].q[0] == (QN{c->P.N, c->P.tsz}) && m.bonds[K].d[0] == 1,
+  DMRG_REQUIRE(m.bonds[K].size() == 1 && m.bonds[K].q[0] == (QN{N, tsz}) && m.bonds[K].d[0] == 1,
                kErrShape, "mps: bond K must be (N, 2Sz) of dim 1");
-  m.site.resize(K);
+  site_size.assign(K, 0);
   for (int b = 0; b < K; ++b) {
     if (b == q->window || b == q->window + 1) continue;
-    const double* src = q->site_data[b];
-    DMRG_REQUIRE(src, kErrInvalidArg, "mps: site tensor pointer is NULL");
+    DMRG_REQUIRE(q->site_data[b], kErrInvalidArg, "mps: site tensor pointer is NULL");
+    const Bond &L = m.bonds[b], &R = m.bonds[b + 1];
+    int64_t off = 0;
+    for (size_t l = 0; l < L.size(); ++l)
+      for (int n = 0; n < 4; ++n) {
+        const int r = R.find(L.q[l] + kSiteQN[n]);
+        if (r >= 0) off += (int64_t)L.d[l] * R.d[r];
+      }
+    DMRG_REQUIRE(off > 0, kErrShape, "mps: a site tensor outside the window has no allowed block");
+    site_size[b] = off;
+  }
+  return m;
+}
+
+static void load_mps(dmrg_ctx c, const dmrg_mps* q) {
+  DMRG_REQUIRE(c->have_problem, kErrState, "mps: load a problem first");
+  std::vector<int64_t> sz;
+  Mps m = parse_mps(c->P.K, c->P.N, c->P.tsz, q, sz);
+  m.site.resize(m.K);
+  for (int b = 0; b < m.K; ++b) {
+    if (b == q->window || b == q->window + 1) continue;
     const Bond &L = m.bonds[b], &R = m.bonds[b + 1];
     SiteTensor& st = m.site[b];
     st.off.assign(4 * L.size(), -1);
@@ -159,7 +220,7 @@ static void load_mps(dmrg_ctx c, const dmrg_mps* q) {
         off += (int64_t)L.d[l] * R.d[r];
       }
     st.data.alloc((size_t)std::max<int64_t>(off, 1) * sizeof(double));
-    DMRG_HIP(hipMemcpy(st.data.p, src, off * sizeof(double), hipMemcpyHostToDevice));
+    DMRG_HIP(hipMemcpy(st.data.p, q->site_data[b], off * sizeof(double), hipMemcpyHostToDevice));
   }
   c->m = std::move(m);
   c->window = q->window;
@@ -432,6 +493,8 @@ dmrg_status dmrg_sigma_get_info(dmrg_ctx c, int32_t precision, dmrg_sigma_info* 
   out->bf_config_stage1 = code(p.bf_choice[0]);
   out->bf_config_stage2 = code(p.bf_choice[1]);
   out->tune_ms = p.tune_ms;
+  out->flops_terms = p.flops_terms;
+  out->flops_stage1_used = p.flops_s1_used;
   out->n_chunks = (int32_t)p.s1.size();
   for (auto& kv : c->left) out->operator_bytes += (int64_t)kv.second->bytes();
   for (auto& kv : c->right) out->operator_bytes += (int64_t)kv.second->bytes();
@@ -499,7 +562,7 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const d
       GemmBatch bt;
       bt.segs.push_back({a, b, lda, ldb, k, flags, alpha});
       bt.add_problem(cc, ldc, m, n, 0, 1, beta);
-      launch_gemm_f64(bt, c->desc, c->stream);
+      launch_gemm_f64(bt, c->stream);
       return kOk;
     }
     if (precision == DMRG_OZAKI) {
@@ -559,6 +622,117 @@ dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const d
     upload_gemm_bf16(bt, d);
     launch_gemm_bf16(d, precision == DMRG_BF16X3, kOutF64, 0, c->stream);
     DMRG_HIP(hipStreamSynchronize(c->stream));
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_validate(const dmrg_problem* problem, const dmrg_mps* mps) {
+  return guarded(nullptr, [&]() -> dmrg_status {
+    validate_problem(problem);
+    if (mps) {
+      std::vector<int64_t> sz;
+      (void)parse_mps(problem->n_orb, problem->n_elec, problem->two_sz, mps, sz);
+    }
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_get_bond(dmrg_ctx c, int32_t bond, int32_t capacity, int32_t* n_sectors,
+                          int32_t* sector_n, int32_t* sector_2sz, int32_t* sector_dim) {
+  if (!c || !n_sectors) return fail(c, kErrInvalidArg, "NULL argument");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->have_mps, kErrState, "get_bond: no MPS loaded");
+    DMRG_REQUIRE(bond >= 0 && bond <= c->P.K, kErrInvalidArg, "get_bond: bond out of range");
+    const Bond& B = c->m.bonds[bond];
+    const int n = (int)B.size();
+    if (sector_n || sector_2sz || sector_dim) {
+      DMRG_REQUIRE(sector_n && sector_2sz && sector_dim, kErrInvalidArg,
+                   "get_bond: give all three sector arrays or none");
+      DMRG_REQUIRE(capacity >= n, kErrShape, "get_bond: capacity below the number of sectors");
+      for (int k = 0; k < n; ++k) {
+        sector_n[k] = B.q[k].n;
+        sector_2sz[k] = B.q[k].s;
+        sector_dim[k] = B.d[k];
+      }
+    }
+    *n_sectors = n;
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_get_site(dmrg_ctx c, int32_t site, int64_t capacity, double* out, int64_t* size) {
+  if (!c || !size) return fail(c, kErrInvalidArg, "NULL argument");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->have_mps, kErrState, "get_site: no MPS loaded");
+    DMRG_REQUIRE(site >= 0 && site < c->P.K, kErrInvalidArg, "get_site: site out of range");
+    DMRG_REQUIRE(site != c->window && site != c->window + 1, kErrState,
+                 "get_site: the window's sites are held in psi, not as site tensors");
+    const SiteTensor& st = c->m.site[site];
+    DMRG_REQUIRE(!st.off.empty(), kErrState, "get_site: the site tensor is not held");
+    const Bond &L = c->m.bonds[site], &R = c->m.bonds[site + 1];
+    // packed size in the dmrg_mps layout (blocks (l, n) -> r, ascending l then n)
+    int64_t n = 0;
+    for (size_t l = 0; l < L.size(); ++l)
+      for (int k = 0; k < 4; ++k) {
+        const int r = R.find(L.q[l] + kSiteQN[k]);
+        if (r >= 0) {
+          DMRG_REQUIRE(st.off[4 * l + k] == n, kErrState, "get_site: internal layout differs from the packed layout");
+          n += (int64_t)L.d[l] * R.d[r];
+        }
+      }
+    if (out) {
+      DMRG_REQUIRE(capacity >= n, kErrShape, "get_site: capacity below the tensor size");
+      DMRG_HIP(hipStreamSynchronize(c->stream));
+      DMRG_HIP(hipMemcpy(out, st.data.p, (size_t)n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    *size = n;
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_energy(dmrg_ctx c, const double* h, const double* eri, const double* psi,
+                        int32_t precision, double* sigma_out, double* grad_psi, double* energy_out,
+                        double* norm2_out) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->plan, kErrState, "energy: call dmrg_build_ops first");
+    DMRG_REQUIRE(psi && energy_out, kErrInvalidArg, "energy: NULL psi or energy_out");
+    DMRG_REQUIRE(precision >= 0 && precision <= 3, kErrInvalidArg, "energy: unknown precision");
+    DMRG_REQUIRE((h == nullptr) == (eri == nullptr), kErrInvalidArg, "energy: give both h and eri or neither");
+    if (h) {
+      const int K = c->P.K;
+      const size_t n1 = (size_t)K * K, n2 = n1 * n1;
+      double dmax = 0, xmax = 0;
+      for (size_t a = 0; a < n1; ++a) {
+        dmax = std::max(dmax, std::fabs(h[a] - c->P.h[a]));
+        xmax = std::max(xmax, std::fabs(c->P.h[a]));
+      }
+      for (size_t a = 0; a < n2; ++a) {
+        dmax = std::max(dmax, std::fabs(eri[a] - c->P.eri[a]));
+        xmax = std::max(xmax, std::fabs(c->P.eri[a]));
+      }
+      DMRG_REQUIRE(dmax <= 1e-13 * std::max(1.0, xmax), kErrInvalidArg,
+                   "energy: h / eri differ from the integrals the operators were built from (max |diff| " +
+                       std::to_string(dmax) + ")");
+    }
+    const int64_t n = c->plan->psi.size;
+    hipStream_t s = c->stream;
+    DevBuf own;
+    double* sig = sigma_out;
+    if (!sig) {
+      own.alloc((size_t)std::max<int64_t>(1, n) * sizeof(double));
+      sig = own.as<double>();
+    }
+    run_sigma(*c->plan, psi, sig, precision, s);
+    DevBuf dots(2 * sizeof(double));
+    launch_multidot(dots.as<double>(), sig, 0, 1, psi, n, s);
+    launch_multidot(dots.as<double>() + 1, psi, 0, 1, psi, n, s);
+    if (grad_psi) launch_axpby(grad_psi, 2.0, sig, 2.0 * c->P.e_core, psi, n, s);
+    double hd[2];
+    DMRG_HIP(hipMemcpyAsync(hd, dots.p, sizeof(hd), hipMemcpyDeviceToHost, s));
+    DMRG_HIP(hipStreamSynchronize(s));
+    *energy_out = hd[0] + c->P.e_core * hd[1];
+    if (norm2_out) *norm2_out = hd[1];
     return kOk;
   });
 }

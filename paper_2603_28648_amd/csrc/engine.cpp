@@ -30,6 +30,7 @@
 #include <map>
 #include <set>
 #include <tuple>
+#include <unordered_set>
 
 namespace dmrg {
 
@@ -213,11 +214,42 @@ void run_projections(int side, const Mps& m, int site, const std::vector<Project
 
 namespace {
 
+// Runs a list of projections whose targets may repeat: rounds in which every
+// target appears once (tiles of one launch must not overlap), each round as
+// few launches as the intermediate budget allows.
+void run_projection_rounds(int side, const Mps& m, int site, std::vector<Projection> projs,
+                           DevBuf& desc, DevBuf& uws, int64_t budget, hipStream_t s) {
+  std::stable_sort(projs.begin(), projs.end(),
+                   [](const Projection& a, const Projection& b) { return a.dst < b.dst; });
+  std::vector<std::vector<Projection>> rounds;
+  for (size_t k = 0; k < projs.size();) {
+    size_t e = k;
+    while (e < projs.size() && projs[e].dst == projs[k].dst) ++e;
+    for (size_t j = k; j < e; ++j) {
+      if (rounds.size() <= j - k) rounds.emplace_back();
+      rounds[j - k].push_back(projs[j]);
+    }
+    k = e;
+  }
+  for (auto& r : rounds) run_projections(side, m, site, r, desc, uws, budget, s);
+}
+
 // Executes all components: new = sum coef * Proj(old (x) y).
+//
+// Components are grouped by (target class, site string, source class).  A
+// group with one source per target is a plain projection; otherwise the
+// cheaper order is taken: with fewer targets than sources the sources are
+// combined first (X = Coef S, one dense GEMM, then X projected), else every
+// source is projected first into a temporary and the temporaries combined
+// into the targets (T += Coef P).  All groups of a step run together: the
+// combinations of every group are one grouped launch, every projection goes
+// into one list (rounds with distinct targets), and the final combinations
+// are grouped launches in rounds with disjoint target rows.  Temporaries are
+// bounded by a budget; groups beyond it run in further batches.
 void execute(const Env& old, Env& neu, const CompMap& cm, const Mps& m, int site,
              DevBuf& desc, hipStream_t s) {
-  const int64_t kBudget = (int64_t)1 << 28;  // doubles of intermediates per chunk (2 GiB)
-  // group by (target class, site string, source class)
+  const int64_t kBudget = (int64_t)1 << 28;     // doubles of projection intermediates (2 GiB)
+  const int64_t kTmpBudget = (int64_t)1 << 28;  // doubles of group temporaries per batch (2 GiB)
   struct Group {
     std::map<int, std::vector<std::pair<int, double>>> by_t;  // target idx -> (src idx, c)
     std::set<int> srcs;
@@ -232,15 +264,23 @@ void execute(const Env& old, Env& neu, const CompMap& cm, const Mps& m, int site
     g.by_t[ti].push_back({si, kv.second});
     g.srcs.insert(si);
   }
-  DevBuf uws, tmp, coef;
+  DevBuf uws;
   std::vector<Projection> direct;
+  struct Multi {
+    const Group* g;
+    int tc, sc, ypar;
+    Mat4 y;
+    bool sum_first;
+    int64_t tmp_doubles;
+  };
+  std::vector<Multi> multi;
   for (auto& gk : groups) {
     const int tc = std::get<0>(gk.first), sc = std::get<2>(gk.first);
     const Str ys = Str::from_key(std::get<1>(gk.first));
     const Mat4 y = site_matrix(ys);
     const int ypar = ys.parity();
-    Group& g = gk.second;
-    OpClass& T = *neu.classes[tc];
+    const Group& g = gk.second;
+    const OpClass& T = *neu.classes[tc];
     const OpClass& S = *old.classes[sc];
     bool single = true;
     for (auto& t : g.by_t) single = single && t.second.size() == 1;
@@ -251,70 +291,128 @@ void execute(const Env& old, Env& neu, const CompMap& cm, const Mps& m, int site
                           t.second[0].second});
       continue;
     }
-    if (nt <= ns) {
-      // sum first: X (nt x nnz_src) = Coef (nt x nops_src) * S, then project
-      std::vector<double> C((size_t)nt * S.nops, 0.0);
-      int row = 0;
-      std::vector<int> tids;
-      for (auto& t : g.by_t) {
-        for (auto& sc2 : t.second) C[(size_t)row * S.nops + sc2.first] += sc2.second;
-        tids.push_back(t.first);
-        ++row;
+    const bool sf = nt <= ns;
+    multi.push_back({&g, tc, sc, ypar, y, sf, sf ? (int64_t)nt * S.L.nnz : (int64_t)ns * T.L.nnz});
+  }
+  DevBuf tmp, coef;
+  std::vector<std::vector<double>> host_coef;  // kept until the stream is synchronised
+  size_t g0 = 0;
+  bool first = true;
+  while (g0 < multi.size() || first) {
+    // one batch of groups within the temporary budget
+    size_t g1 = g0;
+    int64_t need = 0;
+    while (g1 < multi.size() && (g1 == g0 || need + multi[g1].tmp_doubles <= kTmpBudget))
+      need += multi[g1++].tmp_doubles;
+    if (need > 0 && (int64_t)(tmp.bytes / sizeof(double)) < need) {
+      DMRG_HIP(hipStreamSynchronize(s));
+      tmp.alloc((size_t)need * sizeof(double));
+    }
+    // coefficient matrices of the batch in one upload
+    std::vector<double> C;
+    std::vector<int64_t> coff(g1 - g0), toff(g1 - g0);
+    int64_t to = 0;
+    for (size_t q = g0; q < g1; ++q) {
+      const Multi& u = multi[q];
+      const Group& g = *u.g;
+      coff[q - g0] = (int64_t)C.size();
+      toff[q - g0] = to;
+      to += u.tmp_doubles;
+      if (u.sum_first) {
+        const OpClass& S = *old.classes[u.sc];
+        const size_t base = C.size();
+        C.resize(base + g.by_t.size() * (size_t)S.nops, 0.0);
+        int row = 0;
+        for (auto& t : g.by_t) {
+          for (auto& sc2 : t.second) C[base + (size_t)row * S.nops + sc2.first] += sc2.second;
+          ++row;
+        }
+      } else {
+        const int ns = (int)g.srcs.size();
+        std::map<int, int> spos;
+        for (int sid : g.srcs) spos.emplace(sid, (int)spos.size());
+        const int t0 = g.by_t.begin()->first, t1 = g.by_t.rbegin()->first + 1;
+        const size_t base = C.size();
+        C.resize(base + (size_t)(t1 - t0) * ns, 0.0);
+        for (auto& t : g.by_t)
+          for (auto& sc2 : t.second) C[base + (size_t)(t.first - t0) * ns + spos[sc2.first]] += sc2.second;
       }
-      DMRG_HIP(hipStreamSynchronize(s));
-      coef.alloc(C.size() * sizeof(double));
-      DMRG_HIP(hipMemcpy(coef.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
-      tmp.alloc((size_t)std::max<int64_t>(1, (int64_t)nt * S.L.nnz) * sizeof(double));
-      GemmBatch b;
-      b.segs.push_back({coef.p, S.data.p, S.nops, (int)S.L.nnz, S.nops, 0, 1.0});
-      b.add_problem(tmp.p, (int)S.L.nnz, nt, (int)S.L.nnz, 0, 1, 0);
-      launch_gemm_f64(b, desc, s);
-      std::vector<Projection> pj;
-      for (int k = 0; k < nt; ++k)
-        pj.push_back({tmp.as<double>() + (int64_t)k * S.L.nnz, &S.L, y, ypar, T.op(tids[k]), &T.L, 1.0});
-      run_projections(neu.side, m, site, pj, desc, uws, kBudget, s);
-      DMRG_HIP(hipStreamSynchronize(s));
-    } else {
-      // project first: P (ns x nnz_tgt) = Proj(S_j (x) y), then T += Coef * P
-      std::vector<int> sids(g.srcs.begin(), g.srcs.end());
-      std::map<int, int> spos;
-      for (int k = 0; k < ns; ++k) spos[sids[k]] = k;
-      int t0 = g.by_t.begin()->first, t1 = g.by_t.rbegin()->first + 1;
-      std::vector<double> C((size_t)(t1 - t0) * ns, 0.0);
-      for (auto& t : g.by_t)
-        for (auto& sc2 : t.second) C[(size_t)(t.first - t0) * ns + spos[sc2.first]] += sc2.second;
-      DMRG_HIP(hipStreamSynchronize(s));
-      tmp.alloc((size_t)std::max<int64_t>(1, (int64_t)ns * T.L.nnz) * sizeof(double));
-      launch_fill(tmp.as<double>(), 0.0, (int64_t)ns * T.L.nnz, s);
-      std::vector<Projection> pj;
-      for (int k = 0; k < ns; ++k)
-        pj.push_back({S.op(sids[k]), &S.L, y, ypar, tmp.as<double>() + (int64_t)k * T.L.nnz, &T.L, 1.0});
-      run_projections(neu.side, m, site, pj, desc, uws, kBudget, s);
-      coef.alloc(C.size() * sizeof(double));
-      DMRG_HIP(hipMemcpy(coef.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice));
-      GemmBatch b;
-      b.segs.push_back({coef.p, tmp.p, ns, (int)T.L.nnz, ns, 0, 1.0});
-      b.add_problem(T.op(t0), (int)T.L.nnz, t1 - t0, (int)T.L.nnz, 0, 1, 1);
-      launch_gemm_f64(b, desc, s);
-      DMRG_HIP(hipStreamSynchronize(s));
     }
-  }
-  // direct projections: group so that a target appears once per launch
-  std::sort(direct.begin(), direct.end(),
-            [](const Projection& a, const Projection& b) { return a.dst < b.dst; });
-  std::vector<Projection> batch;
-  std::set<double*> seen;
-  for (auto& pr : direct) {
-    if (seen.count(pr.dst)) {
-      run_projections(neu.side, m, site, batch, desc, uws, kBudget, s);
-      batch.clear();
-      seen.clear();
+    if (!C.empty()) {
+      if (coef.bytes < C.size() * sizeof(double)) {
+        DMRG_HIP(hipStreamSynchronize(s));
+        coef.alloc(C.size() * sizeof(double));
+      }
+      DMRG_HIP(hipMemcpyAsync(coef.p, C.data(), C.size() * sizeof(double), hipMemcpyHostToDevice, s));
     }
-    batch.push_back(pr);
-    seen.insert(pr.dst);
+    double* cbase = coef.as<double>();
+    double* tbase = tmp.as<double>();
+    // sum first: X = Coef * S for every such group (one launch)
+    GemmBatch comb;
+    std::vector<Projection> projs;
+    if (first) projs = direct;
+    for (size_t q = g0; q < g1; ++q) {
+      const Multi& u = multi[q];
+      const Group& g = *u.g;
+      const OpClass& S = *old.classes[u.sc];
+      const OpClass& T = *neu.classes[u.tc];
+      double* X = tbase + toff[q - g0];
+      if (u.sum_first) {
+        const int nt = (int)g.by_t.size();
+        const size_t s0 = comb.segs.size();
+        comb.segs.push_back({cbase + coff[q - g0], S.data.p, S.nops, (int)S.L.nnz, S.nops, 0, 1.0});
+        comb.add_problem(X, (int)S.L.nnz, nt, (int)S.L.nnz, s0, s0 + 1, 0);
+        int k = 0;
+        for (auto& t : g.by_t)
+          projs.push_back({X + (int64_t)(k++) * S.L.nnz, &S.L, u.y, u.ypar, T.op(t.first), &T.L, 1.0});
+      } else {
+        // project first into zeroed temporaries
+        launch_fill(X, 0.0, u.tmp_doubles, s);
+        int k = 0;
+        for (int sid : g.srcs)
+          projs.push_back({S.op(sid), &S.L, u.y, u.ypar, X + (int64_t)(k++) * T.L.nnz, &T.L, 1.0});
+      }
+    }
+    launch_gemm_f64(comb, s);
+    run_projection_rounds(neu.side, m, site, std::move(projs), desc, uws, kBudget, s);
+    // project first: T += Coef * P, rounds of disjoint target rows
+    struct Acc {
+      int tc, t0, t1;
+      size_t q;
+    };
+    std::vector<Acc> acc;
+    for (size_t q = g0; q < g1; ++q)
+      if (!multi[q].sum_first)
+        acc.push_back({multi[q].tc, multi[q].g->by_t.begin()->first, multi[q].g->by_t.rbegin()->first + 1, q});
+    while (!acc.empty()) {
+      GemmBatch b;
+      std::vector<Acc> rest;
+      std::map<int, std::vector<std::pair<int, int>>> taken;  // class -> row ranges in this launch
+      for (const Acc& a : acc) {
+        bool clash = false;
+        for (auto& r : taken[a.tc]) clash = clash || (a.t0 < r.second && r.first < a.t1);
+        if (clash) {
+          rest.push_back(a);
+          continue;
+        }
+        taken[a.tc].push_back({a.t0, a.t1});
+        const Multi& u = multi[a.q];
+        const OpClass& T = *neu.classes[u.tc];
+        const int ns = (int)u.g->srcs.size();
+        const size_t s0 = b.segs.size();
+        b.segs.push_back({cbase + coff[a.q - g0], tbase + toff[a.q - g0], ns, (int)T.L.nnz, ns, 0, 1.0});
+        b.add_problem(T.op(a.t0), (int)T.L.nnz, a.t1 - a.t0, (int)T.L.nnz, s0, s0 + 1, 1);
+      }
+      launch_gemm_f64(b, s);
+      acc.swap(rest);
+    }
+    host_coef.push_back(std::move(C));
+    // the next batch reuses tmp and coef
+    DMRG_HIP(hipStreamSynchronize(s));
+    host_coef.clear();
+    g0 = g1;
+    first = false;
   }
-  run_projections(neu.side, m, site, batch, desc, uws, kBudget, s);
-  DMRG_HIP(hipStreamSynchronize(s));
 }
 
 std::vector<int> site_so(int b) { return {2 * b, 2 * b + 1}; }
@@ -528,6 +626,29 @@ static std::vector<size_t> by_key(const AStage& A) {
   return idx;
 }
 
+// FP64 descriptors of one stage (XCD-aware tile order).  Buffer `swap`
+// (if >= 0) is addressed at swap_ptr instead of its own storage.
+static void materialize_f64(const std::vector<PlanBuf>& bufs, const AStage& A, DevGemm& out,
+                            int swap = -1, double* swap_ptr = nullptr) {
+  auto base = [&](int k) { return k == swap ? swap_ptr : bufs[k].f64; };
+  GemmBatch b;
+  b.segs.reserve(A.segs.size());
+  for (auto& g : A.segs)
+    b.segs.push_back({base(g.a.buf) + g.a.off, base(g.b.buf) + g.b.off, g.lda, g.ldb, g.k, g.flags, g.alpha});
+  std::vector<int> keys;
+  for (size_t q : by_key(A)) {
+    const AProb& pb = A.probs[q];
+    b.add_problem(base(pb.c.buf) + pb.c.off, pb.ldc, pb.m, pb.n, (size_t)pb.s0, (size_t)pb.s1, pb.beta);
+    keys.resize(b.tiles.size(), pb.key);
+  }
+  xcd_order(b.tiles, keys, [&](const GemmTile& t) {
+    double c = 0;
+    for (int k = t.seg_begin; k < t.seg_end; ++k) c += b.segs[k].k + 32;
+    return c;
+  });
+  upload_gemm(b, out);
+}
+
 std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env& L, const Env& R,
                                       int64_t ws_budget, hipStream_t s, bool record) {
   const int i = L.bond;
@@ -682,7 +803,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
       GemmBatch b;
       b.segs.push_back({coef.p, Sc.data.p, Sc.nops, (int)Sc.L.nnz, Sc.nops, 0, 1.0});
       b.add_problem(Wc.data.p, (int)Wc.L.nnz, Wc.nops, (int)Wc.L.nnz, 0, 1, 0);
-      launch_gemm_f64(b, desc, s);
+      launch_gemm_f64(b, s);
     }
     DMRG_HIP(hipStreamSynchronize(s));
   }
@@ -840,6 +961,7 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
           off += ps.rows_pad[r] * br.d[rp];
         }
       }
+      std::unordered_set<uint64_t> used;  // (z, r, l, n) row groups of stage 1 read by stage 2
       std::map<std::tuple<int, int64_t>, std::vector<ASeg>> outs;
       std::map<std::tuple<int, int64_t>, int> out_m, out_l;
       auto zin = [&](int z) { return z == -1 ? ci == 0 : (z >= z0 && z < z1); };
@@ -875,6 +997,15 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
                   bref = {BW, it->second + kr->second};
                 }
                 const double sg = ((pr.ypar & 1) && (bl.q[l].n & 1)) ? -1.0 : 1.0;
+                {
+                  // the term's cheaper association order on this psi block
+                  const double a = lb.dr, b = lb.dc, cr = br.d[r], cp = br.d[rp];
+                  plan->flops_terms += pr.z < 0 ? 2.0 * a * b * cr
+                                                : std::min(2.0 * a * b * cr + 2.0 * a * cr * cp,
+                                                           2.0 * b * cr * cp + 2.0 * a * b * cp);
+                  if (pr.z >= 0)
+                    used.insert(((uint64_t)pr.z << 28) | ((uint64_t)r << 16) | ((uint64_t)l << 4) | (uint64_t)n);
+                }
                 auto ok = std::make_tuple(rp, krp->second);
                 outs[ok].push_back({{lref.buf, lref.off + lb.off}, bref, lb.ld, (int)ps.rows_pad[r], lb.dc,
                                     kTransB, yv * sg});
@@ -897,6 +1028,11 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
         st2.probs.push_back({{BS, ps.off_pad[rp] + row * ps.ld[rp]}, ps.ld[rp], mrows, br.d[rp], s0,
                              (int64_t)st2.segs.size(), 1, out_l[o.first]});
       }
+      for (uint64_t u : used) {
+        const int z = (int)(u >> 28), r = (int)((u >> 16) & 0xfff), l = (int)((u >> 4) & 0xfff);
+        const Layout::Blk* zb = plan->zops[z].lay->col(r);
+        if (zb) plan->flops_s1_used += 2.0 * bl.d[l] * br.d[zb->r] * br.d[r];
+      }
       plan->flops += st1.flops + st2.flops;
       plan->flops_stage1 += st1.flops;
       plan->flops_stage2 += st2.flops;
@@ -911,38 +1047,19 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     plan->p1 = std::move(a1[0]);
     plan->p2 = std::move(a2[0]);
   }
-  // FP64 descriptors
-  auto mat64 = [&](const AStage& A, DevGemm& out) {
-    GemmBatch b;
-    b.segs.reserve(A.segs.size());
-    for (auto& g : A.segs)
-      b.segs.push_back({plan->bufs[g.a.buf].f64 + g.a.off, plan->bufs[g.b.buf].f64 + g.b.off,
-                        g.lda, g.ldb, g.k, g.flags, g.alpha});
-    std::vector<int> keys;
-    for (size_t q : by_key(A)) {
-      const AProb& pb = A.probs[q];
-      b.add_problem(plan->bufs[pb.c.buf].f64 + pb.c.off, pb.ldc, pb.m, pb.n, (size_t)pb.s0,
-                    (size_t)pb.s1, pb.beta);
-      keys.resize(b.tiles.size(), pb.key);
-    }
-    xcd_order(b.tiles, keys, [&](const GemmTile& t) {
-      double c = 0;
-      for (int k = t.seg_begin; k < t.seg_end; ++k) c += b.segs[k].k + 32;
-      return c;
-    });
-    upload_gemm(b, out);
-  };
   plan->f64_s1.resize(plan->s1.size());
   plan->f64_s2.resize(plan->s2.size());
   for (size_t c = 0; c < plan->s1.size(); ++c) {
-    mat64(plan->s1[c], plan->f64_s1[c]);
-    mat64(plan->s2[c], plan->f64_s2[c]);
+    materialize_f64(plan->bufs, plan->s1[c], plan->f64_s1[c]);
+    materialize_f64(plan->bufs, plan->s2[c], plan->f64_s2[c]);
   }
-  mat64(plan->p1, plan->f64_p1);
-  mat64(plan->p2, plan->f64_p2);
+  materialize_f64(plan->bufs, plan->p1, plan->f64_p1);
+  materialize_f64(plan->bufs, plan->p2, plan->f64_p2);
   DMRG_HIP(hipStreamSynchronize(s));
   return plan;
 }
+
+
 
 // Tile shape of one output problem in the mixed configuration: the shape
 // with the least padded area per unit of its dense throughput (relative
@@ -1523,5 +1640,6 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
   }
   DMRG_HIP(hipGraphLaunch(ex, s));
 }
+
 
 }  // namespace dmrg

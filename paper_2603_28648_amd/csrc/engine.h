@@ -409,6 +409,10 @@ struct SigmaPlan {
   bool diag_ready = false;
   double flops = 0;            // algorithmic FLOPs of one sigma
   double flops_stage1 = 0, flops_stage2 = 0;
+  // sum over (term, psi block) of the cheaper of the two association orders
+  double flops_terms = 0;
+  // stage-1 FLOPs of the rows stage 2 reads (stage 1 multiplies whole psi sectors)
+  double flops_s1_used = 0;
   int64_t ws_doubles = 0;
   // kept for the backward
   std::vector<OpRef> zrefs;    // right-block operator of each zops entry

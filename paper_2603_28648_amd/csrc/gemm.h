@@ -134,10 +134,11 @@ void xcd_order(std::vector<Tile>& tiles, const std::vector<int>& key, Cost&& cos
   tiles.swap(out);
 }
 
-// Launch (stream-ordered).  dev_scratch holds the uploaded descriptors; it is
-// grown as needed; the call returns after the launch is enqueued and the
-// descriptor copies have completed.
-void launch_gemm_f64(const GemmBatch& b, DevBuf& dev_scratch, hipStream_t stream);
+// Launch (stream-ordered, no host synchronisation).  The descriptors are
+// copied into pinned staging memory of the library, so the caller may
+// release b as soon as the call returns; operand and output buffers must stay
+// valid until the launch has run.
+void launch_gemm_f64(const GemmBatch& b, hipStream_t stream);
 
 // Descriptors uploaded once and launched many times (no host work per launch).
 struct DevGemm {
@@ -154,6 +155,9 @@ void launch_gemm_f64(const DevGemm& d, hipStream_t stream, int role = 0);
 void launch_scale(double* x, double a, int64_t n, hipStream_t s);
 void launch_axpy(double* y, double a, const double* x, int64_t n, hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+// z = a x + b y (z may alias x or y)
+void launch_axpby(double* z, double a, const double* x, double b, const double* y, int64_t n,
+                  hipStream_t s);
 // out[j] = sum_i X[j][i] * y[i] for j < nv (X rows of length n, row stride ldx)
 void launch_multidot(double* out, const double* X, int64_t ldx, int nv, const double* y,
                      int64_t n, hipStream_t s);

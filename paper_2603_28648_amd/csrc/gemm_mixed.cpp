@@ -116,7 +116,7 @@ GemmPrecisionScope::~GemmPrecisionScope() { g_scope = nullptr; }
 
 void launch_gemm(const GemmBatch& b, DevBuf& desc, hipStream_t s) {
   if (!g_scope || g_scope->precision == 0 || b.tiles.empty()) {
-    launch_gemm_f64(b, desc, s);
+    launch_gemm_f64(b, s);
     return;
   }
   launch_gemm_lowp(b, *g_scope, s);

@@ -1,6 +1,9 @@
 // gfx950 kernels: FP64-MFMA grouped GEMM and FP64 BLAS-1 helpers.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+#include <map>
+
 #include <algorithm>
 
 #include "gemm.h"
@@ -148,29 +151,66 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
       }
 }
 
-void launch_gemm_f64(const GemmBatch& b, DevBuf& scratch, hipStream_t stream) {
+// Descriptors of one-off launches go through a ring of pinned host buffers
+// copied asynchronously to device buffers, so that a launch needs no host
+// synchronisation: a slot is reused only after the event recorded behind
+// the launch that read it has completed.  One ring per device and host
+// thread, kept until the process ends.
+namespace {
+struct DescSlot {
+  char* host = nullptr;
+  DevBuf dev;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool used = false;
+};
+constexpr int kDescSlots = 8;
+struct DescRing {
+  DescSlot slot[kDescSlots];
+  int next = 0;
+};
+DescRing& desc_ring() {
+  static thread_local std::map<int, DescRing*> rings;
+  int dev = 0;
+  DMRG_HIP(hipGetDevice(&dev));
+  DescRing*& r = rings[dev];
+  if (!r) r = new DescRing();  // process lifetime
+  return *r;
+}
+}  // namespace
+
+void launch_gemm_f64(const GemmBatch& b, hipStream_t stream) {
   if (b.tiles.empty()) return;
   const size_t sb = b.segs.size() * sizeof(GemmSeg);
+  const size_t sba = ((sb + 255) / 256) * 256;
   const size_t tb = b.tiles.size() * sizeof(GemmTile);
-  const size_t need = sb + tb + 256;
-  if (scratch.bytes < need) {
-    DMRG_HIP(hipStreamSynchronize(stream));
-    scratch.alloc(need);
+  const size_t need = sba + tb;
+  DescRing& ring = desc_ring();
+  DescSlot& sl = ring.slot[ring.next];
+  ring.next = (ring.next + 1) % kDescSlots;
+  if (sl.used) DMRG_HIP(hipEventSynchronize(sl.ev));
+  if (!sl.ev) DMRG_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+  if (sl.cap < need) {
+    const size_t cap = std::max(need, (size_t)1 << 16);
+    if (sl.host) DMRG_HIP(hipHostFree(sl.host));
+    sl.host = nullptr;
+    DMRG_HIP(hipHostMalloc(reinterpret_cast<void**>(&sl.host), cap));
+    sl.dev.alloc(cap);
+    sl.cap = cap;
   }
-  char* base = scratch.as<char>();
-  GemmSeg* dsegs = reinterpret_cast<GemmSeg*>(base);
-  GemmTile* dtiles = reinterpret_cast<GemmTile*>(base + ((sb + 255) / 256) * 256);
-  DMRG_HIP(hipMemcpyAsync(dsegs, b.segs.data(), sb, hipMemcpyHostToDevice, stream));
-  DMRG_HIP(hipMemcpyAsync(dtiles, b.tiles.data(), tb, hipMemcpyHostToDevice, stream));
+  std::memcpy(sl.host, b.segs.data(), sb);
+  std::memcpy(sl.host + sba, b.tiles.data(), tb);
+  DMRG_HIP(hipMemcpyAsync(sl.dev.p, sl.host, need, hipMemcpyHostToDevice, stream));
+  GemmSeg* dsegs = sl.dev.as<GemmSeg>();
+  GemmTile* dtiles = reinterpret_cast<GemmTile*>(sl.dev.as<char>() + sba);
   const size_t nt = b.tiles.size();
   for (size_t off = 0; off < nt; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(nt - off, (size_t)1 << 30);
     hipLaunchKernelGGL(k_gemm_f64<0>, dim3(cnt), dim3(256), 0, stream, dtiles + off, dsegs);
   }
   DMRG_HIP(hipGetLastError());
-  // descriptors come from pageable host memory: make sure the copies are done
-  // before the caller may release or reuse the host vectors
-  DMRG_HIP(hipStreamSynchronize(stream));
+  DMRG_HIP(hipEventRecord(sl.ev, stream));
+  sl.used = true;
 }
 
 void upload_gemm(const GemmBatch& b, DevGemm& d) {
@@ -211,6 +251,12 @@ __global__ void k_axpy(double* y, double a, const double* x, int64_t n) {
        i += (int64_t)gridDim.x * blockDim.x)
     y[i] += a * x[i];
 }
+__global__ void k_axpby(double* z, double a, const double* x, double b, const double* y,
+                        int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = a * x[i] + b * y[i];
+}
 __global__ void k_fill(double* x, double v, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -230,6 +276,12 @@ void launch_scale(double* x, double a, int64_t n, hipStream_t s) {
 void launch_axpy(double* y, double a, const double* x, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, s, y, a, x, n);
+  DMRG_HIP(hipGetLastError());
+}
+void launch_axpby(double* z, double a, const double* x, double b, const double* y, int64_t n,
+                  hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, s, z, a, x, b, y, n);
   DMRG_HIP(hipGetLastError());
 }
 void launch_fill(double* x, double v, int64_t n, hipStream_t s) {

@@ -122,7 +122,7 @@ TruncResult truncate_and_move(Mps& m, int window, const double* psi, int dir, in
     else  // rho = M^T M
       b.segs.push_back({S.M.p, S.M.p, S.ncol, S.ncol, S.nrow, kTransA, 1.0});
     b.add_problem(S.rho.p, n, n, n, 0, 1, 0);
-    launch_gemm_f64(b, scratch, s);
+    launch_gemm_f64(b, s);
     S.eval.alloc((size_t)std::max(1, n) * sizeof(double));
     DevBuf work((size_t)std::max(1, n) * sizeof(double));
     check_rb(rocsolver_dsyevd(sh.h, rocblas_evect_original, rocblas_fill_upper, n, S.rho.as<double>(), n,
@@ -218,7 +218,7 @@ TruncResult truncate_and_move(Mps& m, int window, const double* psi, int dir, in
       bc.segs.push_back({S.rho.as<double>() + (int64_t)j0 * S.nrow, S.M.p, S.nrow, S.ncol, S.nrow, 0, 1.0});
       bc.add_problem(c.p, S.ncol, S.kept, S.ncol, s0, s0 + 1, 0);
     }
-    launch_gemm_f64(bc, scratch, s);
+    launch_gemm_f64(bc, s);
     GemmBatch bp;
     for (size_t rp = 0; rp < b3.size(); ++rp)
       for (auto& kv : np.row_of[rp]) {
@@ -236,7 +236,7 @@ TruncResult truncate_and_move(Mps& m, int window, const double* psi, int dir, in
         bp.add_problem(next_psi.as<double>() + np.off[rp] + kv.second * b3.d[rp], b3.d[rp], nb.d[q], b3.d[rp],
                        s0, s0 + 1, 0);
       }
-    launch_gemm_f64(bp, scratch, s);
+    launch_gemm_f64(bp, s);
     DMRG_HIP(hipStreamSynchronize(s));
     m.site[i] = std::move(A);
     m.bonds[i + 1] = nb;
@@ -288,7 +288,7 @@ TruncResult truncate_and_move(Mps& m, int window, const double* psi, int dir, in
       bc.segs.push_back({S.M.p, S.rho.as<double>() + (int64_t)j0 * S.ncol, S.ncol, S.ncol, S.ncol, kTransB, 1.0});
       bc.add_problem(c.p, S.kept, S.nrow, S.kept, s0, s0 + 1, 0);
     }
-    launch_gemm_f64(bc, scratch, s);
+    launch_gemm_f64(bc, s);
     GemmBatch bp;
     for (size_t q = 0; q < nb.size(); ++q)
       for (auto& kv : np.row_of[q]) {
@@ -305,7 +305,7 @@ TruncResult truncate_and_move(Mps& m, int window, const double* psi, int dir, in
         bp.add_problem(next_psi.as<double>() + np.off[q] + kv.second * nb.d[q], nb.d[q], b0.d[lp], nb.d[q],
                        s0, s0 + 1, 0);
       }
-    launch_gemm_f64(bp, scratch, s);
+    launch_gemm_f64(bp, s);
     DMRG_HIP(hipStreamSynchronize(s));
     m.site[i + 1] = std::move(B);
     m.bonds[i + 1] = nb;

@@ -5,7 +5,7 @@ analysis of sweep energies; no device work).
   subsequent sweeps agree, max(|E_s - E_(s-1)|, |E_(s-1) - E_(s-2)|) < tol,
   with tol = 1e-5 Ha in the paper.
 * The two extrapolations to the truncation-free limit (Numerical benchmark
-  section, Fig. 4): a second-order polynomial in 1/D evaluated at 1/D = 0,
+  section, Fig. 2): a second-order polynomial in 1/D evaluated at 1/D = 0,
   and a second-order polynomial in the largest truncation error of the last
   sweep evaluated at zero truncation error.
 """

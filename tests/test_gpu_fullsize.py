@@ -1,7 +1,9 @@
-"""The sigma at the full benchmark shape: CAS(54,36) (36 orbitals, 54
-electrons, 2S_z = 0), bond dimension 4096, middle window (17, 18), in the
-launch configuration the benchmark times (autotuned BF16 tiles, graph
-replay).
+"""The sigma at the full benchmark shapes, in the launch configuration the
+benchmark times (autotuned BF16 tiles, graph replay):
+* CAS(54,36) (36 orbitals, 54 electrons), bond dimension 4096, middle window
+  (17, 18), at 2S_z = 0 (the headline) and 2S_z = 4 (the S_z = 2 state);
+* CAS(22,22) (22 orbitals and electrons, 2S_z = 0), bond dimension 1024,
+  middle window (10, 11).
 
 The oracle cannot build environments at D = 4096 in reasonable time, so
 these tests check properties that hold at any size:
@@ -22,8 +24,10 @@ from synthetic import make_integrals, make_mps, mps_arrays, pack_psi
 
 pytestmark = pytest.mark.gpu
 
-K, N, TSZ, D, WINDOW = 36, 54, 0, 4096, 17
-ISEED, MSEED = 36, 1036
+# K, N, 2Sz, D, window, integral seed, MPS seed
+CONFIGS = {"cas54_36": (36, 54, 0, 4096, 17, 36, 1036),
+           "cas54_36_sz2": (36, 54, 4, 4096, 17, 36, 1036),
+           "cas22_22": (22, 22, 0, 1024, 10, 22, 1022)}
 
 # number-operator Hamiltonian: h = NUMBER_C 1, (pq|rs) = NUMBER_U d_pq d_rs
 NUMBER_C, NUMBER_U = 0.3, 0.01
@@ -31,16 +35,17 @@ NUMBER_C, NUMBER_U = 0.3, 0.01
 REL_TOL = {"bf16": 3e-3, "bf16x3": 2e-5, "ozaki": 1e-12}
 
 
-@pytest.fixture(scope="module")
-def big():
-    """A context of its own (freed at the end of the module) with the
-    operators of the benchmark workload."""
+@pytest.fixture(scope="module", params=list(CONFIGS))
+def big(request):
+    """A context of its own (freed after the configuration's tests) with the
+    operators of one benchmark workload."""
     import torch
     from paper_2603_28648_amd import Context
+    K, N, TSZ, D, WINDOW, ISEED, MSEED = CONFIGS[request.param]
     print(f"full-size sigma: K={K} N={N} 2Sz={TSZ} D={D} window={WINDOW}", flush=True)
     m = make_mps(K, N, TSZ, D, WINDOW, MSEED)
     c = Context(0)
-    state = {"ctx": c, "mps": m, "ops": None}
+    state = {"ctx": c, "mps": m, "ops": None, "cfg": CONFIGS[request.param]}
     yield state
     torch.cuda.synchronize()
     c.close()
@@ -51,6 +56,7 @@ def _load(state, name):
     the number-operator Hamiltonian ("number"), unless they are loaded."""
     if state["ops"] == name:
         return
+    K, N, TSZ, D, WINDOW, ISEED, MSEED = state["cfg"]
     if name == "real":
         h, eri = make_integrals(K, ISEED)
     else:
@@ -75,6 +81,7 @@ def test_fullsize_number_operator_closed_form(big):
     import torch
     _load(big, "number")
     c, m = big["ctx"], big["mps"]
+    K, N, TSZ, D, WINDOW = big["cfg"][:5]
     lam = NUMBER_C * N + 0.5 * NUMBER_U * N * (N - 1)
     psi = torch.from_numpy(pack_psi(m.bonds, WINDOW, m.psi)).cuda()
     psi /= torch.linalg.norm(psi)
@@ -93,6 +100,7 @@ def test_fullsize_symmetry_and_precisions(big):
     import torch
     _load(big, "real")
     c, m = big["ctx"], big["mps"]
+    WINDOW = big["cfg"][4]
     psi = torch.from_numpy(pack_psi(m.bonds, WINDOW, m.psi)).cuda()
     psi /= torch.linalg.norm(psi)
     s64 = _sigma(c, psi, "fp64")
@@ -124,6 +132,7 @@ def test_fullsize_graph_replay_bitwise(big):
     import torch
     _load(big, "real")
     c, m = big["ctx"], big["mps"]
+    WINDOW = big["cfg"][4]
     psi = torch.from_numpy(pack_psi(m.bonds, WINDOW, m.psi)).cuda()
     for prec in ("bf16x3", "fp64"):
         c.sigma_graphs(False)

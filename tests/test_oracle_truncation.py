@@ -171,3 +171,19 @@ def test_planted_mistake_in_the_guess_is_caught():
     v0 = psi_to_fock(m, m.psi)
     v1 = psi_to_fock(bad["mps"], bad["mps"].psi)
     assert abs((v0 - v1) @ (v0 - v1) - good["eps"]) > 1e-3
+
+
+def test_stored_oracle_sigma_reproduces():
+    """The stored oracle results of tests/golden/ (used by the GPU parity test
+    at 22 and 36 orbitals) are the oracle's: one file recomputed here."""
+    import os
+    from oracle.blocksparse import BlockSparseSigma
+    from synthetic import make_integrals, pack_psi
+    path = os.path.join(os.path.dirname(__file__), "golden", "sigma_k22_n22_sz0_d48_w10.npz")
+    z = np.load(path)
+    K, N, tsz, D, i, iseed, mseed = (int(v) for v in z["case"])
+    h, eri = make_integrals(K, iseed)
+    m = make_mps(K, N, tsz, D, i, mseed)
+    assert np.array_equal(pack_psi(m.bonds, i, m.psi), z["psi"])
+    sig = pack_psi(m.bonds, i, BlockSparseSigma(m, h, eri).apply(m.psi))
+    assert np.max(np.abs(sig - z["sigma"])) <= 1e-13 * np.max(np.abs(sig))
