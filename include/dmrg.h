@@ -228,6 +228,21 @@ typedef struct {
 dmrg_status dmrg_davidson(dmrg_ctx ctx, double* psi_inout, const dmrg_davidson_opts* opts,
                           double* energy_out, dmrg_davidson_stats* stats_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * sigma of dmrg_sigma (same kernels, same result) with its stage-1 workspace
+ * in a fixed 64 MiB device array that the library holds per GPU until the
+ * process ends.  The call itself allocates nothing: its descriptors are built
+ * by dmrg_build_ops.  psi, sigma: device pointers as for dmrg_sigma.  A window
+ * whose stage-1 workspace (one chunk) exceeds 64 MiB is refused with
+ * DMRG_ERR_SHAPE; create the context with DMRG_WS_BUDGET_MB <= 64 to chunk
+ * it below that.  Every context on a GPU shares that GPU's array, so calls
+ * that overlap on one GPU (from several contexts or streams) race; calls
+ * ordered on one stream do not.  Graph replay (dmrg_sigma_graphs) and kernel
+ * timing do not apply.  Stream-ordered, no synchronisation (except when the
+ * psi / sigma pointers differ from the previous call's). */
+dmrg_status dmrg_sigma_noalloc(dmrg_ctx ctx, const double* psi, double* sigma);
+
 /* Reverse mode of the sigma with respect to the integrals.  For window
  * vectors psi and sigma_bar (device, psi layout of the current window;
  * sigma_bar NULL means psi) and the current MPS, f = <sigma_bar, H_eff psi>

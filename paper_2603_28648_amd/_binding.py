@@ -89,6 +89,7 @@ EXPORTS = {
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
     "dmrg_psi_size": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
     "dmrg_sigma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "dmrg_sigma_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_sigma_get_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(SigmaInfo)]),
     "dmrg_davidson": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(DavidsonOpts),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(DavidsonStats)]),
@@ -243,6 +244,11 @@ class Context:
     def sigma(self, psi, out, precision="fp64"):
         p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self._check(self.lib.dmrg_sigma(self.h, _dev_ptr(psi), _dev_ptr(out), p), self.h)
+        return out
+
+    def sigma_noalloc(self, psi, out):
+        """FP64 sigma through dmrg_sigma_noalloc (no device allocation)."""
+        self._check(self.lib.dmrg_sigma_noalloc(self.h, _dev_ptr(psi), _dev_ptr(out)), self.h)
         return out
 
     def orbital_gradient(self, dh, deri):

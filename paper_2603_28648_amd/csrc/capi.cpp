@@ -13,6 +13,7 @@
 #include "backward.h"
 #include "davidson.h"
 #include "engine.h"
+#include "noalloc.h"
 #include "truncate.h"
 
 using namespace dmrg;
@@ -83,6 +84,17 @@ dmrg_status dmrg_create(dmrg_ctx* out, int32_t device, void* stream) {
   if (!c) return fail(nullptr, kErrOom, "host allocation failed");
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
+  // device address of the no-allocation scratch, looked up with the device current
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return fail(nullptr, kErrHip, "hipSetDevice failed");
+  }
+  try {
+    noalloc_scratch_init(device);
+  } catch (const Error& e) {
+    delete c;
+    return fail(nullptr, e.code, e.what());
+  }
   if (const char* b = std::getenv("DMRG_WS_BUDGET_MB")) c->ws_budget = std::atoll(b) * (1 << 17);
   *out = c;
   return kOk;
@@ -296,6 +308,7 @@ dmrg_status dmrg_build_ops(dmrg_ctx c, const dmrg_problem* problem, const dmrg_m
     const double t0 = now_s();
     c->plan = plan_sigma(c->P, c->m, *c->left[site], *c->right[site + 2], c->ws_budget, s);
     c->plan->use_graphs = c->use_graphs;
+    plan_fixed_workspace(*c->plan, noalloc_scratch(c->device), kNoAllocScratchDoubles);
     DMRG_HIP(hipStreamSynchronize(s));
     if (verbose())
       fprintf(stderr, "[dmrg] sigma plan: %.2f s, %zu pairs, %zu right ops, %.3e flops\n",
@@ -320,6 +333,22 @@ dmrg_status dmrg_sigma(dmrg_ctx c, const double* psi, double* sigma, int32_t pre
     DMRG_REQUIRE(psi && sigma, kErrInvalidArg, "sigma: NULL buffer");
     DMRG_REQUIRE(precision >= 0 && precision <= 3, kErrInvalidArg, "sigma: unknown precision");
     run_sigma(*c->plan, psi, sigma, precision, c->stream);
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_sigma_noalloc(dmrg_ctx c, const double* psi, double* sigma) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(c->plan, kErrState, "sigma_noalloc: call dmrg_build_ops first");
+    DMRG_REQUIRE(psi && sigma, kErrInvalidArg, "sigma_noalloc: NULL buffer");
+    DMRG_REQUIRE(c->plan->fx_ready, kErrShape,
+                 "sigma_noalloc: the window's stage-1 workspace (" +
+                     std::to_string((c->plan->ws_doubles * 8) >> 20) +
+                     " MiB per chunk) exceeds the fixed scratch (" +
+                     std::to_string((kNoAllocScratchDoubles * 8) >> 20) +
+                     " MiB); create the context with DMRG_WS_BUDGET_MB at most that size");
+    run_sigma_fixed_workspace(*c->plan, psi, sigma, c->stream);
     return kOk;
   });
 }

@@ -1059,6 +1059,20 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
   return plan;
 }
 
+bool plan_fixed_workspace(SigmaPlan& plan, double* ws, int64_t ws_doubles) {
+  plan.fx_ready = false;
+  if (!ws || plan.ws_doubles > ws_doubles) return false;
+  plan.fx_s1.resize(plan.s1.size());
+  plan.fx_s2.resize(plan.s2.size());
+  for (size_t c = 0; c < plan.s1.size(); ++c) {
+    materialize_f64(plan.bufs, plan.s1[c], plan.fx_s1[c], plan.buf_ws, ws);
+    materialize_f64(plan.bufs, plan.s2[c], plan.fx_s2[c], plan.buf_ws, ws);
+  }
+  materialize_f64(plan.bufs, plan.p1, plan.fx_p1, plan.buf_ws, ws);
+  materialize_f64(plan.bufs, plan.p2, plan.fx_p2, plan.buf_ws, ws);
+  plan.fx_ready = true;
+  return true;
+}
 
 
 // Tile shape of one output problem in the mixed configuration: the shape
@@ -1641,5 +1655,21 @@ void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision,
   DMRG_HIP(hipGraphLaunch(ex, s));
 }
 
+void run_sigma_fixed_workspace(SigmaPlan& plan, const double* psi, double* sigma, hipStream_t s) {
+  DMRG_REQUIRE(plan.fx_ready, kErrState, "sigma: no fixed-workspace schedule");
+  if (plan.bound_sigma != sigma) DMRG_HIP(hipStreamSynchronize(s));
+  bind_tasks(plan.unpack_host, plan.unpack_tasks, nullptr, sigma, false, plan.bound_sigma);
+  bind_psi(plan, psi, s);
+  enqueue_load_psi(plan, s);
+  PlanBuf& S = plan.bufs[plan.buf_sig];
+  launch_fill(S.f64, 0.0, S.n, s);
+  launch_gemm_f64(plan.fx_p1, s, 1);
+  launch_gemm_f64(plan.fx_p2, s, 2);
+  for (size_t c = 0; c < plan.fx_s1.size(); ++c) {
+    launch_gemm_f64(plan.fx_s1[c], s, 1);
+    launch_gemm_f64(plan.fx_s2[c], s, 2);
+  }
+  launch_copy_tasks(plan.unpack_tasks.as<CopyTask>(), plan.n_pack, false, s);
+}
 
 }  // namespace dmrg

@@ -405,6 +405,11 @@ struct SigmaPlan {
   std::vector<std::vector<DevGemmB>> bf_s1, bf_s2;  // per chunk: one launch per tile shape
   bool bf_ready = false;
   OzPlan oz;
+  // FP64 schedule with the stage-1 workspace at a caller-given fixed address
+  // (descriptors built at plan time, so running it allocates nothing)
+  std::vector<DevGemm> fx_s1, fx_s2;
+  DevGemm fx_p1, fx_p2;
+  bool fx_ready = false;
   DevBuf diag;                 // diag(H_eff) for the Davidson preconditioner
   bool diag_ready = false;
   double flops = 0;            // algorithmic FLOPs of one sigma
@@ -436,6 +441,13 @@ void plan_load_psi(SigmaPlan& plan, const double* psi, hipStream_t s);
 // on INT8 (block Hamiltonian pairs stay FP64 in 1-3).
 void run_sigma(SigmaPlan& plan, const double* psi, double* sigma, int precision, hipStream_t s);
 void prepare_bf16(SigmaPlan& plan, hipStream_t s);
+// Builds the FP64 descriptors of the plan's schedule with the stage-1
+// workspace at ws (ws_doubles doubles) instead of the plan's own buffer;
+// false (and nothing built) when the plan's workspace does not fit.
+bool plan_fixed_workspace(SigmaPlan& plan, double* ws, int64_t ws_doubles);
+// FP64 sigma on that schedule: host work only binds the caller's buffers
+// (task-list copies when the pointers change); no device allocation.
+void run_sigma_fixed_workspace(SigmaPlan& plan, const double* psi, double* sigma, hipStream_t s);
 // Slices per operand (kappa digits, DMRG_OZAKI_SLICES, default 6) and the
 // Ozaki task lists of both stages.
 void prepare_ozaki(SigmaPlan& plan, hipStream_t s);
