@@ -331,10 +331,13 @@ class Context:
         self._check(self.lib.dmrg_get_psi(self.h, _dev_ptr(out)), self.h)
         return out
 
-    def _half_sweeps(self, psi, n_half, max_bond_dim, tol, ladder, log, refine=False):
+    def _half_sweeps(self, psi, n_half, max_bond_dim, tol, ladder, log, refine=False, max_iter=100):
         """n_half half-sweeps from the loaded window; per half-sweep: energy of
-        its last window, lowest energy, largest truncation error, and the
-        seconds spent in the eigensolver and in operator construction."""
+        its last window, lowest energy, largest truncation error, the seconds
+        spent in the eigensolver and in operator construction, and one record
+        per window of its eigensolver result (converged, iterations,
+        residual): a window that stops at max_iter without reaching tol is
+        counted in "unconverged", never silently dropped."""
         import time
         import torch
         K = self._n_orb
@@ -344,13 +347,16 @@ class Context:
         direction = -1 if site == K - 2 else +1
         for _ in range(n_half):
             e_last, e_min, eps_max, t_dav, t_build = None, np.inf, 0.0, 0.0, 0.0
+            windows = []
             while True:
                 t0 = time.perf_counter()
-                r = self.davidson(cur, tol=tol, ladder=ladder, refine=refine)
+                r = self.davidson(cur, tol=tol, ladder=ladder, refine=refine, max_iter=max_iter)
                 torch.cuda.synchronize()
                 t_dav += time.perf_counter() - t0
                 e_last = r["energy"]
                 e_min = min(e_min, e_last)
+                windows.append({"window": site, "converged": r["converged"], "iterations": r["iterations"],
+                                "residual": r["residual"]})
                 at_end = (direction > 0 and site == K - 2) or (direction < 0 and site == 0)
                 move = -direction if at_end else direction
                 eps, kept = self.truncate(cur, move, max_bond_dim)
@@ -363,51 +369,66 @@ class Context:
                 cur = torch.empty(self.psi_size(), dtype=torch.float64, device=cur.device)
                 self.get_psi(cur)
                 if log:
-                    log(f"window {site - move} E={e_last:.12f} eps={eps:.2e} D={kept}")
+                    log(f"window {site - move} E={e_last:.12f} eps={eps:.2e} D={kept} "
+                        f"residual={r['residual']:.1e}{'' if r['converged'] else ' (not converged)'}")
                 if at_end:
                     direction = move
                     break
             out.append({"energy": e_last, "min_energy": e_min, "max_trunc": eps_max,
-                        "davidson_s": t_dav, "build_s": t_build})
+                        "davidson_s": t_dav, "build_s": t_build, "windows": windows,
+                        "unconverged": sum(1 for w in windows if not w["converged"])})
         return out, cur
 
     def sweep(self, psi, n_sweeps, max_bond_dim, tol=1e-6, ladder=(("fp64", None),), log=None,
-              refine=False):
-        """Two-site sweeps from the loaded window; returns per-half-sweep energies.
+              refine=False, max_iter=100):
+        """Two-site sweeps from the loaded window; returns per-half-sweep
+        energies, largest truncation errors, and the final window vector.
 
         psi: device tensor of the current window; the context's window must be
         0 (start of a left-to-right sweep).  Each half-sweep optimises every
         window once and turns at the chain end."""
-        halves, cur = self._half_sweeps(psi, 2 * n_sweeps, max_bond_dim, tol, ladder, log, refine)
+        halves, cur = self._half_sweeps(psi, 2 * n_sweeps, max_bond_dim, tol, ladder, log, refine, max_iter)
+        self.last_halves = halves
         return [h["energy"] for h in halves], [h["max_trunc"] for h in halves], cur
 
     def sweep_to_convergence(self, psi, max_bond_dim, sweep_tol=1e-5, max_sweeps=20, tol=1e-6,
-                             ladder=(("fp64", None),), log=None, refine=False):
+                             ladder=(("fp64", None),), log=None, refine=False, max_iter=100,
+                             require_converged=False):
         """Full sweeps (there and back) until the energies of three subsequent
         sweeps agree within sweep_tol (the paper's stopping rule, 1e-5 Ha).
         E_s is the lowest energy met in sweep s, eps_s its largest truncation
-        error.  Returns a dict with the per-sweep records, whether the rule was
-        met, and the final window vector.  log (optional) receives one line
-        per sweep.  refine: residual refinement in every window's eigensolver
-        (see davidson)."""
+        error.  Returns a dict with the per-sweep records (each with the count
+        of windows whose eigensolver stopped at max_iter before tol), whether
+        the rule was met, the total of such windows, and the final window
+        vector.  log (optional) receives one line per sweep.  refine: residual
+        refinement in every window's eigensolver (see davidson).
+        require_converged: raise RuntimeError when a window's eigensolver
+        does not converge."""
         from .extrapolate import sweep_converged
         sweeps = []
         cur = psi
         while len(sweeps) < max_sweeps:
-            halves, cur = self._half_sweeps(cur, 2, max_bond_dim, tol, ladder, None, refine)
+            halves, cur = self._half_sweeps(cur, 2, max_bond_dim, tol, ladder, None, refine, max_iter)
             sweeps.append({"min_energy": min(h["min_energy"] for h in halves),
                            "max_trunc": max(h["max_trunc"] for h in halves),
                            "davidson_s": sum(h["davidson_s"] for h in halves),
-                           "build_s": sum(h["build_s"] for h in halves)})
+                           "build_s": sum(h["build_s"] for h in halves),
+                           "unconverged": sum(h["unconverged"] for h in halves),
+                           "max_residual": max(w["residual"] for h in halves for w in h["windows"])})
+            sw = sweeps[-1]
             if log:
-                sw = sweeps[-1]
                 log(f"sweep {len(sweeps)}: E={sw['min_energy']:.12f} eps={sw['max_trunc']:.2e} "
-                    f"eigensolver {sw['davidson_s']:.1f} s, operators {sw['build_s']:.1f} s")
-            if sweep_converged([sw["min_energy"] for sw in sweeps], sweep_tol):
+                    f"eigensolver {sw['davidson_s']:.1f} s, operators {sw['build_s']:.1f} s, "
+                    f"unconverged windows {sw['unconverged']} (largest residual {sw['max_residual']:.1e})")
+            if require_converged and sw["unconverged"]:
+                raise RuntimeError(f"sweep {len(sweeps)}: {sw['unconverged']} windows did not reach "
+                                   f"residual {tol} in {max_iter} iterations")
+            if sweep_converged([s_["min_energy"] for s_ in sweeps], sweep_tol):
                 break
         converged = sweep_converged([sw["min_energy"] for sw in sweeps], sweep_tol)
         return {"sweeps": sweeps, "converged": converged, "energy": sweeps[-1]["min_energy"],
-                "max_trunc": sweeps[-1]["max_trunc"], "psi": cur}
+                "max_trunc": sweeps[-1]["max_trunc"], "psi": cur,
+                "unconverged_windows": sum(sw["unconverged"] for sw in sweeps)}
 
     def get_bond(self, bond):
         """Sectors of a bond of the context's MPS: list of (N, 2Sz, dim)."""

@@ -943,6 +943,33 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     for (size_t ci = 0; ci < chunk_list.size(); ++ci) {
       const int z0 = chunk_list[ci].first, z1 = chunk_list[ci].second;
       AStage st1, st2;
+      auto zin = [&](int z) { return z == -1 ? ci == 0 : (z >= z0 && z < z1); };
+      // The row groups (l, n) of each Psi_r that stage 2 reads through right
+      // operator z: stage 1 computes only those rows of T_{z,r}.
+      std::map<std::pair<int, int>, std::map<int64_t, int>> reads;  // (z, r) -> padded row -> d_l
+      for (auto& pz : pairs_of_z) {
+        if (pz.first < 0 || !zin(pz.first)) continue;
+        const Layout& Zl = *plan->zops[pz.first].lay;
+        for (int k : pz.second) {
+          const SigmaPair& pr = plan->pairs[k];
+          for (int np = 0; np < 16; ++np)
+            for (int n = 0; n < 16; ++n) {
+              if (pr.y.m[np][n] == 0) continue;
+              const QN qn = kSiteQN[n >> 2] + kSiteQN[n & 3];
+              const QN qnp = kSiteQN[np >> 2] + kSiteQN[np & 3];
+              for (auto& lb : pr.L.lay->blk) {
+                const int l = lb.c, lp = lb.r;
+                const int r = br.find(bl.q[l] + qn), rp = br.find(bl.q[lp] + qnp);
+                if (r < 0 || rp < 0) continue;
+                auto kr = ps.row_pad_of[r].find({l, n});
+                if (kr == ps.row_pad_of[r].end() || !ps.row_pad_of[rp].count({lp, np})) continue;
+                const Layout::Blk* zb = Zl.col(r);
+                if (!zb || zb->r != rp) continue;
+                reads[{pz.first, r}][kr->second] = bl.d[l];
+              }
+            }
+        }
+      }
       std::map<std::pair<int, int>, int64_t> tloc;  // (z, r) -> ws offset of T^T (d_r' x rows_pad_r)
       int64_t off = 0;
       for (int z = z0; z < z1; ++z) {
@@ -951,20 +978,39 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
         for (auto& blk : Z.lay->blk) {
           const int r = blk.c, rp = blk.r;
           if (ps.rows_of[r] == 0 || ps.rows_of[rp] == 0) continue;
+          auto rd = reads.find({z, r});
+          if (rd == reads.end()) continue;  // no pair reads T_{z,r}
           tloc[{z, r}] = off;
           const double alpha = (plan->zpar[z] && (br.q[r].n & 1)) ? -1.0 : 1.0;
-          const int64_t s0 = (int64_t)st1.segs.size();
-          st1.segs.push_back({ref_of(Z.data + blk.off), {BP, ps.off_pad[r]}, blk.ld, ps.ld[r], br.d[r], kTransB, alpha});
-          // key: the psi sector, so that Psi_r stays in one XCD's L2
-          st1.probs.push_back({{BW, off}, (int)ps.rows_pad[r], br.d[rp], (int)ps.rows_pad[r], s0, s0 + 1, 0, r});
-          st1.flops += 2.0 * ps.rows_of[r] * br.d[rp] * br.d[r];
+          // column ranges of T^T (padded psi rows): the groups read, merged
+          // across gaps of at most kGap rows
+          constexpr int64_t kGap = 32;
+          std::vector<std::pair<int64_t, int64_t>> ranges;
+          for (auto& g : rd->second) {
+            const int64_t a = g.first, b = g.first + pad8(g.second);
+            if (!ranges.empty() && a - ranges.back().second <= kGap) ranges.back().second = std::max(ranges.back().second, b);
+            else ranges.push_back({a, b});
+          }
+          for (auto& rg : ranges) {
+            const int64_t s0 = (int64_t)st1.segs.size();
+            st1.segs.push_back({ref_of(Z.data + blk.off), {BP, ps.off_pad[r] + rg.first * ps.ld[r]}, blk.ld,
+                                ps.ld[r], br.d[r], kTransB, alpha});
+            // key: the psi sector, so that Psi_r stays in one XCD's L2
+            st1.probs.push_back({{BW, off + rg.first}, (int)ps.rows_pad[r], br.d[rp], (int)(rg.second - rg.first),
+                                 s0, s0 + 1, 0, r});
+          }
+          // real (unpadded) psi rows multiplied
+          int64_t rows = 0;
+          for (auto& g : ps.row_pad_of[r])
+            for (auto& rg : ranges)
+              if (g.second >= rg.first && g.second < rg.second) rows += bl.d[g.first.first];
+          st1.flops += 2.0 * rows * br.d[rp] * br.d[r];
           off += ps.rows_pad[r] * br.d[rp];
         }
       }
       std::unordered_set<uint64_t> used;  // (z, r, l, n) row groups of stage 1 read by stage 2
       std::map<std::tuple<int, int64_t>, std::vector<ASeg>> outs;
       std::map<std::tuple<int, int64_t>, int> out_m, out_l;
-      auto zin = [&](int z) { return z == -1 ? ci == 0 : (z >= z0 && z < z1); };
       for (auto& pz : pairs_of_z) {
         if (!zin(pz.first)) continue;
         for (int k : pz.second) {

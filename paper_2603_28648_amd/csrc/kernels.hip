@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
   const GemmTile t = tiles[blockIdx.x];
   if (t.m <= 0) return;  // padding tile of the XCD-ordered launch
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   const int lr = lane & 15, lk = lane >> 4;
   f64x4 acc[2][2];
@@ -113,16 +113,26 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
       }
       const bool more = ns < t.seg_end;
       if (more) load(ng, nk0);  // in flight during the MFMAs below
+      // MFMAs only on 16x16 blocks and k-steps of 4 that meet the tile's
+      // valid rows, columns and the segment's k (the rest of the LDS slab is
+      // zero padding); the conditions are uniform over the wave, so the
+      // skipped MFMAs leave the SIMD's matrix pipe to the other waves
+      if (wm < t.m && wn < t.n) {
+        const int kv = g.k - k0;  // valid k of this slab (>= 1)
 #pragma unroll
-      for (int kk = 0; kk < kTK; kk += 4) {
-        const double a0 = As[buf][kk + lk][wm + lr];
-        const double a1 = As[buf][kk + lk][wm + 16 + lr];
-        const double b0 = Bs[buf][kk + lk][wn + lr];
-        const double b1 = Bs[buf][kk + lk][wn + 16 + lr];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        for (int kk = 0; kk < kTK; kk += 4) {
+          if (kk >= kv) break;
+          const double a0 = As[buf][kk + lk][wm + lr];
+          const double a1 = As[buf][kk + lk][wm + 16 + lr];
+          const double b0 = Bs[buf][kk + lk][wn + lr];
+          const double b1 = Bs[buf][kk + lk][wn + 16 + lr];
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+          if (wn + 16 < t.n) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+          if (wm + 16 < t.m) {
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            if (wn + 16 < t.n) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+          }
+        }
       }
       if (!more) break;
       // the other buffer was last read before the previous barrier

@@ -37,6 +37,9 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-6, help="Davidson residual per window")
     ap.add_argument("--ladder", default="mixed", choices=sorted(LADDERS))
+    ap.add_argument("--max-iter", type=int, default=100,
+                    help="eigensolver iterations per window (residual refinement counts each inner "
+                         "product); windows that stop short of --tol are counted in the output")
     args = ap.parse_args()
 
     import torch
@@ -67,17 +70,20 @@ def main():
         t0 = time.perf_counter()
         ladder, refine = LADDERS[args.ladder]
         r = ctx.sweep_to_convergence(psi, D, sweep_tol=args.sweep_tol, max_sweeps=args.max_sweeps,
-                                     tol=args.tol, ladder=ladder, log=sweep_log, refine=refine)
+                                     tol=args.tol, ladder=ladder, log=sweep_log, refine=refine,
+                                     max_iter=args.max_iter)
         wall = time.perf_counter() - t0
         sw = r["sweeps"]
         rec = {"bond_dim": D, "sweeps": len(sw), "converged": r["converged"], "energy": r["energy"],
                "max_trunc": r["max_trunc"], "energies": [s["min_energy"] for s in sw],
                "build_ops_s_per_sweep": sum(s["build_s"] for s in sw) / len(sw),
                "davidson_s_per_sweep": sum(s["davidson_s"] for s in sw) / len(sw),
-               "initial_build_s": t_init, "wall_s": wall}
+               "initial_build_s": t_init, "wall_s": wall,
+               "unconverged_windows": r["unconverged_windows"],
+               "unconverged_per_sweep": [s["unconverged"] for s in sw]}
         print(json.dumps(rec), flush=True)
         log(f"[sweeps] D={D}: {len(sw)} sweeps, E={r['energy']:.10f}, eps={r['max_trunc']:.2e}, "
-            f"converged={r['converged']}, {wall:.0f} s")
+            f"converged={r['converged']}, {wall:.0f} s, windows not converged: {r['unconverged_windows']}")
         E.append(r["energy"])
         eps.append(r["max_trunc"])
     summary = {"config": args.config, "ladder": args.ladder, "bond_dims": ds, "energies": E,

@@ -43,3 +43,12 @@ def test_no_device_is_an_error_not_a_fallback():
     st = lib.dmrg_create(ctypes.byref(h), 0, None)
     assert st == -5  # DMRG_ERR_NO_DEVICE
     assert b"device" in lib.dmrg_last_error(None).lower()
+
+
+def test_binding_calls_every_export():
+    """Each exported call has a binding that uses it (argument marshalling
+    for tests and the benchmark), so none is declared but unreachable."""
+    import inspect
+    src = inspect.getsource(_binding)
+    unused = [n for n in _binding.EXPORTS if f"lib.{n}(" not in src]
+    assert not unused, unused

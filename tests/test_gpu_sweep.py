@@ -18,6 +18,8 @@ def _run(ctx, D, D_init, n_sweeps):
     ctx.build_ops(0, h=h, eri=eri, n_elec=8, two_sz=0, mps_arrays=mps_arrays(m))
     psi = torch.from_numpy(pack_psi(m.bonds, 0, m.psi)).cuda()
     E, eps, _ = ctx.sweep(psi, n_sweeps, D, tol=1e-8)
+    # every window's eigensolver reached its tolerance
+    assert all(hs["unconverged"] == 0 for hs in ctx.last_halves), ctx.last_halves
     return h, eri, E, eps
 
 
@@ -53,6 +55,7 @@ def test_refined_sweeps_reach_fci_at_complete_bond_dimension(ctx):
     ctx.build_ops(0, h=h, eri=eri, n_elec=8, two_sz=0, mps_arrays=mps_arrays(m))
     psi = torch.from_numpy(pack_psi(m.bonds, 0, m.psi)).cuda()
     E, eps, _ = ctx.sweep(psi, 3, 256, tol=1e-8, ladder=(("bf16x3", 1e-4), ("fp64", None)), refine=True)
+    assert all(hs["unconverged"] == 0 for hs in ctx.last_halves)
     e_fci = fci(8, 8, 0, h, eri)[0][0]
     print(f"  E per half-sweep {[round(e, 12) for e in E]} FCI {e_fci:.12f}", flush=True)
     assert abs(E[-1] - e_fci) < 1e-9

@@ -38,6 +38,7 @@ def test_sweeps_converge_and_extrapolate_toward_fci(ctx):
         print(f"  D={D}: {len(sw)} sweeps, E={r['energy']:.10f} (E-E_FCI={r['energy'] - e_fci:.2e}) "
               f"eps={r['max_trunc']:.2e} converged={r['converged']}", flush=True)
         assert r["converged"]
+        assert r["unconverged_windows"] == 0  # every window's eigensolver reached 1e-8
         assert r["energy"] >= e_fci - 1e-9  # variational
         E.append(r["energy"])
         eps.append(r["max_trunc"])
