@@ -47,19 +47,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(kernel_src, config):
+def profiled_traffic(sources, config):
     """HBM bytes per sigma of the BF16 grouped GEMM from the committed
-    rocprofv3 summary, if it was taken with this kernel source and launch
-    configuration (else None)."""
+    rocprofv3 summary, if it was taken with these sources (the kernel and the
+    schedule that builds its launches) and launch configuration (else None)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "k_gemm_bf16_sigma_cas54_36_D4096.md")
     try:
         text = open(path).read()
-        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for src in sources:
+            h.update(open(src, "rb").read())
+        sha = h.hexdigest()
     except OSError:
         return None
-    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    m_sha = re.search(r"sources_sha256:\s*([0-9a-f]+)", text)
     m_cfg = re.search(r"bf16_launch_config:\s*(\d+),(\d+)", text)
     m_tr = re.search(r"traffic_bytes_per_sigma:\s*([0-9.eE+]+)", text)
     m_ln = re.search(r"launches_per_sigma:\s*(\d+)", text)
@@ -385,7 +388,8 @@ def main():
     peak = PEAK_TFLOPS[args.precision]
     traffic = None
     if args.precision != "fp64" and args.config == "cas54_36":
-        pt = profiled_traffic(os.path.join(ROOT, "paper_2603_28648_amd", "csrc", "kernels_bf16.hip"),
+        csrc = os.path.join(ROOT, "paper_2603_28648_amd", "csrc")
+        pt = profiled_traffic([os.path.join(csrc, "kernels_bf16.hip"), os.path.join(csrc, "engine.cpp")],
                               (tuned["stage1"], tuned["stage2"]))
         if pt is not None:
             traffic = pt[0] / pt[1]  # bytes per chunk-stage launch

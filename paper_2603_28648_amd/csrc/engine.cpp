@@ -1052,6 +1052,8 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
                   if (pr.z >= 0)
                     used.insert(((uint64_t)pr.z << 28) | ((uint64_t)r << 16) | ((uint64_t)l << 4) | (uint64_t)n);
                 }
+                if (LI && pr.lsrc == 0 && pr.lref.cls == LI->cls && pr.lref.idx == LI->idx)
+                  plan->flops_s2_ident += 2.0 * lb.dr * br.d[rp] * lb.dc;
                 auto ok = std::make_tuple(rp, krp->second);
                 outs[ok].push_back({{lref.buf, lref.off + lb.off}, bref, lb.ld, (int)ps.rows_pad[r], lb.dc,
                                     kTransB, yv * sg});
@@ -1087,6 +1089,24 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
     }
   };
   schedule(false, chunks, plan->s1, plan->s2);
+  if (std::getenv("DMRG_VERBOSE") && std::atoi(std::getenv("DMRG_VERBOSE")) > 1) {
+    // per chunk: FLOPs of both stages, output problems, and the longest
+    // segment list of stage 2 (summed k)
+    for (size_t c = 0; c < plan->s1.size(); ++c) {
+      const AStage& a = plan->s2[c];
+      int64_t kmax = 0, ksum = 0;
+      for (auto& pb : a.probs) {
+        int64_t k = 0;
+        for (int64_t q = pb.s0; q < pb.s1; ++q) k += a.segs[q].k;
+        kmax = std::max(kmax, k);
+        ksum += k;
+      }
+      fprintf(stderr, "[dmrg] chunk %zu: stage 1 %.3e flop, %zu problems; stage 2 %.3e flop, %zu problems, "
+              "summed k per problem max %lld mean %.0f\n", c, plan->s1[c].flops, plan->s1[c].probs.size(),
+              a.flops, a.probs.size(), (long long)kmax, a.probs.empty() ? 0.0 : (double)ksum / a.probs.size());
+    }
+    fprintf(stderr, "[dmrg] stage-2 FLOPs with the left identity as operand: %.3e\n", plan->flops_s2_ident);
+  }
   {
     std::vector<AStage> a1, a2;
     schedule(true, {{0, nz}}, a1, a2);

