@@ -139,9 +139,10 @@ typedef struct {
   /* BF16 launch configuration per stage, chosen by the autotuner on the
    * first mixed-precision sigma of the window (until then the default):
    * tile shape (0: 128x64, 1: 64x64, 2: 64x128, 3: 128x128, 4: 128x128 with
-   * three LDS stages, 5: chosen per output problem, 6: 128x128 over the
-   * whole 128-blocks of each output problem and 64-wide tiles over
-   * remainders of at most 64 rows or columns) + 16 * tile grouping
+   * three LDS stages, 5: 256x256 with eight waves (stage 2; stage 1 then
+   * uses 4), 6: chosen per output problem, 7: 128x128 over the whole
+   * 128-blocks of each output problem and 64-wide tiles over remainders of
+   * at most 64 rows or columns) + 16 * tile grouping
    * (0: per output problem, 1: per operand-sharing key) + 256 * segment
    * order (1: sorted by operand) */
   int32_t bf_config_stage1, bf_config_stage2;

@@ -628,10 +628,25 @@ static std::vector<size_t> by_key(const AStage& A) {
 
 // FP64 descriptors of one stage (XCD-aware tile order).  Buffer `swap`
 // (if >= 0) is addressed at swap_ptr instead of its own storage.
+// Output tile of the FP64 sigma stages (stage 1, stage 2): measured at
+// CAS(54,36) D=4096, the 128 x 128 eight-wave tile is faster for stage 1
+// (309 against 355 ms per sigma) and the 64 x 64 four-wave tile for stage 2
+// (578 against 611 ms).  DMRG_F64_TILE="t1,t2" (64 or 128 each) overrides.
+static int f64_sigma_tile(int stage) {
+  int t[2] = {128, 64};
+  if (const char* e = std::getenv("DMRG_F64_TILE")) {
+    DMRG_REQUIRE(std::sscanf(e, "%d,%d", &t[0], &t[1]) == 2 && (t[0] == 64 || t[0] == 128) &&
+                     (t[1] == 64 || t[1] == 128),
+                 kErrInvalidArg, "DMRG_F64_TILE must be \"t1,t2\" with 64 or 128 each");
+  }
+  return t[stage - 1];
+}
+
 static void materialize_f64(const std::vector<PlanBuf>& bufs, const AStage& A, DevGemm& out,
-                            int swap = -1, double* swap_ptr = nullptr) {
+                            int swap = -1, double* swap_ptr = nullptr, int tile = kTileM) {
   auto base = [&](int k) { return k == swap ? swap_ptr : bufs[k].f64; };
   GemmBatch b;
+  b.tile = tile;
   b.segs.reserve(A.segs.size());
   for (auto& g : A.segs)
     b.segs.push_back({base(g.a.buf) + g.a.off, base(g.b.buf) + g.b.off, g.lda, g.ldb, g.k, g.flags, g.alpha});
@@ -1116,8 +1131,8 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
   plan->f64_s1.resize(plan->s1.size());
   plan->f64_s2.resize(plan->s2.size());
   for (size_t c = 0; c < plan->s1.size(); ++c) {
-    materialize_f64(plan->bufs, plan->s1[c], plan->f64_s1[c]);
-    materialize_f64(plan->bufs, plan->s2[c], plan->f64_s2[c]);
+    materialize_f64(plan->bufs, plan->s1[c], plan->f64_s1[c], -1, nullptr, f64_sigma_tile(1));
+    materialize_f64(plan->bufs, plan->s2[c], plan->f64_s2[c], -1, nullptr, f64_sigma_tile(2));
   }
   materialize_f64(plan->bufs, plan->p1, plan->f64_p1);
   materialize_f64(plan->bufs, plan->p2, plan->f64_p2);
@@ -1131,8 +1146,8 @@ bool plan_fixed_workspace(SigmaPlan& plan, double* ws, int64_t ws_doubles) {
   plan.fx_s1.resize(plan.s1.size());
   plan.fx_s2.resize(plan.s2.size());
   for (size_t c = 0; c < plan.s1.size(); ++c) {
-    materialize_f64(plan.bufs, plan.s1[c], plan.fx_s1[c], plan.buf_ws, ws);
-    materialize_f64(plan.bufs, plan.s2[c], plan.fx_s2[c], plan.buf_ws, ws);
+    materialize_f64(plan.bufs, plan.s1[c], plan.fx_s1[c], plan.buf_ws, ws, f64_sigma_tile(1));
+    materialize_f64(plan.bufs, plan.s2[c], plan.fx_s2[c], plan.buf_ws, ws, f64_sigma_tile(2));
   }
   materialize_f64(plan.bufs, plan.p1, plan.fx_p1, plan.buf_ws, ws);
   materialize_f64(plan.bufs, plan.p2, plan.fx_p2, plan.buf_ws, ws);
@@ -1144,12 +1159,21 @@ bool plan_fixed_workspace(SigmaPlan& plan, double* ws, int64_t ws_doubles) {
 // Tile shape of one output problem in the mixed configuration: the shape
 // with the least padded area per unit of its dense throughput (relative
 // rates of the shapes measured on large GEMMs).
-static int mixed_shape(int m, int n) {
-  static const int cand[4] = {kShape128x128, kShape128x64, kShape64x128, kShape64x64};
-  static const double rate[4] = {1.0, 0.72, 0.72, 0.62};
-  int best = kShape128x128;
+static int mixed_shape(int m, int n, bool fp64_out) {
+  // BF16-output stages (stage 1): four shapes, relative dense throughput;
+  // FP64-output stages (stage 2): the 256 x 256 tile (twice the operand reuse
+  // per byte of 128 x 128, measured 1.1x faster over a whole stage) or the
+  // three-stage 128 x 128 tile, whichever pads the problem less per unit of
+  // throughput
+  static const int cand1[4] = {kShape128x128, kShape128x64, kShape64x128, kShape64x64};
+  static const double rate1[4] = {1.0, 0.72, 0.72, 0.62};
+  static const int cand2[2] = {kShape256x256, kShape128x128s3};
+  static const double rate2[2] = {1.5, 1.0};
+  const int* cand = fp64_out ? cand2 : cand1;
+  const double* rate = fp64_out ? rate2 : rate1;
+  int best = cand[0];
   double bc = 1e300;
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < (fp64_out ? 2 : 4); ++q) {
     const int BM = shape_rows(cand[q]), BN = shape_cols(cand[q]);
     const double c = (double)((m + BM - 1) / BM * BM) * ((n + BN - 1) / BN * BN) / rate[q];
     if (c < bc) { bc = c; best = cand[q]; }
@@ -1193,9 +1217,11 @@ static void build_bf_stage(SigmaPlan& plan, int stage, const BfChoice& ch,
   out.resize(st.size());
   for (size_t ci = 0; ci < st.size(); ++ci) {
     const AStage& A = st[ci];
-    std::vector<int> pshape(A.probs.size(), ch.shape);
+    // stage 1 writes BF16 hi/lo, which the eight-wave 256 x 256 tile does not
+    const int uni = (stage == 1 && ch.shape == kShape256x256) ? kShape128x128s3 : ch.shape;
+    std::vector<int> pshape(A.probs.size(), uni);
     if (ch.shape == kShapeMixed)
-      for (size_t q = 0; q < A.probs.size(); ++q) pshape[q] = mixed_shape(A.probs[q].m, A.probs[q].n);
+      for (size_t q = 0; q < A.probs.size(); ++q) pshape[q] = mixed_shape(A.probs[q].m, A.probs[q].n, stage == 2);
     std::vector<size_t> order(A.probs.size());
     for (size_t q = 0; q < order.size(); ++q) order[q] = q;
     if (ch.order == 1) order = by_key(A);
@@ -1489,7 +1515,8 @@ static void autotune_bf16(SigmaPlan& plan, hipStream_t s) {
       plan.tune_log.push_back({stage, c, t});
       if (t < tbest) { tbest = t; best = c; }
     };
-    for (int sh = 0; sh <= kShapeSplit; ++sh) trial(BfChoice{sh, 0, 0});
+    for (int sh = 0; sh <= kShapeSplit; ++sh)
+      if (!(stage == 1 && sh == kShape256x256)) trial(BfChoice{sh, 0, 0});
     const int sh = best.shape;
     trial(BfChoice{sh, 1, 0});
     if (stage == 2) {
@@ -1512,7 +1539,7 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
     if (b.is_operator) launch_split_bf16(b.bf.as<uint16_t>(), b.f64, b.n, s);
     else launch_fill(reinterpret_cast<double*>(b.bf.p), 0.0, (int64_t)(b.bf.bytes / sizeof(double)), s);
   }
-  // DMRG_BF16_SHAPE=0|1|2 fixes the tile shape of both stages (tests of each
+  // DMRG_BF16_SHAPE=0..7 fixes the tile shape of both stages (tests of each
   // kernel variant); otherwise DMRG_AUTOTUNE=0|1 switches the autotuner off or
   // on (default: on for plans above 5e10 FLOP per sigma).
   // DMRG_BF16_CONFIG="c1,c2" fixes the configuration of both stages (codes of
@@ -1535,7 +1562,7 @@ void prepare_bf16(SigmaPlan& plan, hipStream_t s) {
     }
   } else if (fixed) {
     const int sh = std::atoi(fixed);
-    DMRG_REQUIRE(sh >= 0 && sh <= kShapeSplit, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0 to 6");
+    DMRG_REQUIRE(sh >= 0 && sh <= kShapeSplit, kErrInvalidArg, "DMRG_BF16_SHAPE must be 0 to 7");
     plan.bf_choice[0].shape = plan.bf_choice[1].shape = sh;
   } else if (env ? std::atoi(env) != 0 : plan.flops > 5e10) {
     autotune_bf16(plan, s);

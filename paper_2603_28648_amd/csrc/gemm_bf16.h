@@ -9,13 +9,18 @@ namespace dmrg {
 
 enum : int { kOutBf16 = 0, kOutF64 = 1 };
 // Workgroup tile shapes of the BF16 kernel (rows x columns of the output).
-// kShape128x128s3: the 128 x 128 tile with three LDS stages instead of two.
+// kShape128x128s3: the 128 x 128 tile with three LDS stages instead of two;
+// kShape256x256: eight waves, FP64 output only (sigma stage 2).
 enum : int {
   kShape128x64 = 0, kShape64x64 = 1, kShape64x128 = 2, kShape128x128 = 3, kShape128x128s3 = 4,
-  kNumShapes = 5
+  kShape256x256 = 5, kNumShapes = 6
 };
-inline int shape_rows(int s) { return (s == kShape128x64 || s >= kShape128x128) ? 128 : 64; }
-inline int shape_cols(int s) { return (s == kShape64x128 || s >= kShape128x128) ? 128 : 64; }
+inline int shape_rows(int s) {
+  return s == kShape256x256 ? 256 : (s == kShape128x64 || s >= kShape128x128) ? 128 : 64;
+}
+inline int shape_cols(int s) {
+  return s == kShape256x256 ? 256 : (s == kShape64x128 || s >= kShape128x128) ? 128 : 64;
+}
 
 // NT operands: A row-major m x k (stride lda), B stored n x k (stride ldb),
 // rows 16-byte aligned and zero-padded in k to a multiple of 8.

@@ -14,37 +14,45 @@ namespace dmrg {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// One workgroup (4 waves) per 64x64 output tile; each wave owns a 32x32
-// quarter as 2x2 blocks of v_mfma_f64_16x16x4f64.  Operands are staged
-// through LDS in k-slabs of 16 with bounds-checked (zero-filled) loads, so
-// ragged m, n, k need no padding in memory.  alpha is folded into A.  The
-// slabs of all segments of a tile form one sequence, double-buffered: the
-// global loads of the next slab are issued into registers before the MFMAs
-// of the current one, then stored into the other LDS buffer (one barrier per
-// slab).
+// One workgroup per TM x TM output tile: 64 x 64 with 4 waves (each a 32 x 32
+// quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64) or 128 x 128 with 8 waves
+// (each 64 x 32 as 4 x 2 blocks; twice the operand reuse per loaded byte).
+// Operands are staged through LDS in k-slabs of 16 with bounds-checked
+// (zero-filled) loads, so ragged m, n, k need no padding in memory.  alpha is
+// folded into A.  The slabs of all segments of a tile form one sequence,
+// double-buffered: the global loads of the next slab are issued into
+// registers before the MFMAs of the current one, then stored into the other
+// LDS buffer (one barrier per slab).
 //
 // MFMA operand layout (16x16x4 f64, wave64): lane l supplies A[l%16][l/16]
 // and B[l/16][l%16]; accumulator element v of lane l holds D[4*v + l/16][l%16]
 // (rows interleaved across the four 16-lane groups).
 constexpr int kTK = 16;
-constexpr int kLoadsA = (kTileM * kTK) / 256, kLoadsB = (kTileN * kTK) / 256;
+constexpr int f64_waves(int TM) { return TM == 128 ? 8 : 4; }
 
 // ROLE only names the kernel for profilers: 0 = operator construction,
 // 1 = sigma stage 1 (psi x right operator), 2 = sigma stage 2 (left operator x T).
-template <int ROLE>
-__global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ tiles,
-                                                   const GemmSeg* __restrict__ segs) {
-  __shared__ double As[2][kTK][kTileM + 1];
-  __shared__ double Bs[2][kTK][kTileN + 1];
+template <int ROLE, int TM>
+__global__ __launch_bounds__(64 * f64_waves(TM)) void k_gemm_f64(const GemmTile* __restrict__ tiles,
+                                                                 const GemmSeg* __restrict__ segs) {
+  constexpr int TN = TM;
+  constexpr int WV = f64_waves(TM), NT = 64 * WV;
+  constexpr int WC = WV / 2;                        // waves across the columns
+  constexpr int FM = TM / 32, FN = TN / (16 * WC);  // 16x16 blocks of a wave
+  constexpr int kLoadsA = (TM * kTK) / NT, kLoadsB = (TN * kTK) / NT;
+  __shared__ double As[2][kTK][TM + 1];
+  __shared__ double Bs[2][kTK][TN + 1];
   const GemmTile t = tiles[blockIdx.x];
   if (t.m <= 0) return;  // padding tile of the XCD-ordered launch
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave / WC) * (TM / 2), wn = (wave % WC) * (TN / WC);
   const int lr = lane & 15, lk = lane >> 4;
-  f64x4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+  f64x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 
   if (t.seg_begin < t.seg_end) {
     double ra[kLoadsA], rb[kLoadsB];
@@ -55,10 +63,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
       const bool ta = g.flags & kTransA, tb = g.flags & kTransB;
 #pragma unroll
       for (int r = 0; r < kLoadsA; ++r) {
-        const int e = r * 256 + tid;
+        const int e = r * NT + tid;
         int i, kk;
         if (!ta) { i = e / kTK; kk = e % kTK; }
-        else { kk = e / kTileM; i = e % kTileM; }
+        else { kk = e / TM; i = e % TM; }
         const int gk = k0 + kk;
         double v = 0.0;
         if (i < t.m && gk < g.k) {
@@ -69,9 +77,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
       }
 #pragma unroll
       for (int r = 0; r < kLoadsB; ++r) {
-        const int e = r * 256 + tid;
+        const int e = r * NT + tid;
         int j, kk;
-        if (!tb) { kk = e / kTileN; j = e % kTileN; }
+        if (!tb) { kk = e / TN; j = e % TN; }
         else { j = e / kTK; kk = e % kTK; }
         const int gk = k0 + kk;
         double v = 0.0;
@@ -87,14 +95,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
       const bool ta = g.flags & kTransA, tb = g.flags & kTransB;
 #pragma unroll
       for (int r = 0; r < kLoadsA; ++r) {
-        const int e = r * 256 + tid;
+        const int e = r * NT + tid;
         if (!ta) As[buf][e % kTK][e / kTK] = ra[r];
-        else As[buf][e / kTileM][e % kTileM] = ra[r];
+        else As[buf][e / TM][e % TM] = ra[r];
       }
 #pragma unroll
       for (int r = 0; r < kLoadsB; ++r) {
-        const int e = r * 256 + tid;
-        if (!tb) Bs[buf][e / kTileN][e % kTileN] = rb[r];
+        const int e = r * NT + tid;
+        if (!tb) Bs[buf][e / TN][e % TN] = rb[r];
         else Bs[buf][e % kTK][e / kTK] = rb[r];
       }
     };
@@ -122,16 +130,18 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
 #pragma unroll
         for (int kk = 0; kk < kTK; kk += 4) {
           if (kk >= kv) break;
-          const double a0 = As[buf][kk + lk][wm + lr];
-          const double a1 = As[buf][kk + lk][wm + 16 + lr];
-          const double b0 = Bs[buf][kk + lk][wn + lr];
-          const double b1 = Bs[buf][kk + lk][wn + 16 + lr];
-          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-          if (wn + 16 < t.n) acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-          if (wm + 16 < t.m) {
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            if (wn + 16 < t.n) acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-          }
+          double a[FM], b[FN];
+#pragma unroll
+          for (int i = 0; i < FM; ++i) a[i] = As[buf][kk + lk][wm + 16 * i + lr];
+#pragma unroll
+          for (int j = 0; j < FN; ++j) b[j] = Bs[buf][kk + lk][wn + 16 * j + lr];
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+            if (wm + 16 * i < t.m)
+#pragma unroll
+              for (int j = 0; j < FN; ++j)
+                if (wn + 16 * j < t.n)
+                  acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
       }
       if (!more) break;
@@ -146,9 +156,9 @@ __global__ __launch_bounds__(256) void k_gemm_f64(const GemmTile* __restrict__ t
   }
   double* __restrict__ C = static_cast<double*>(t.c);
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < FM; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int bj = 0; bj < FN; ++bj)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = wm + bi * 16 + 4 * v + lk;
@@ -216,7 +226,10 @@ void launch_gemm_f64(const GemmBatch& b, hipStream_t stream) {
   const size_t nt = b.tiles.size();
   for (size_t off = 0; off < nt; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(nt - off, (size_t)1 << 30);
-    hipLaunchKernelGGL(k_gemm_f64<0>, dim3(cnt), dim3(256), 0, stream, dtiles + off, dsegs);
+    if (b.tile == 128)
+      hipLaunchKernelGGL((k_gemm_f64<0, 128>), dim3(cnt), dim3(512), 0, stream, dtiles + off, dsegs);
+    else
+      hipLaunchKernelGGL((k_gemm_f64<0, 64>), dim3(cnt), dim3(256), 0, stream, dtiles + off, dsegs);
   }
   DMRG_HIP(hipGetLastError());
   DMRG_HIP(hipEventRecord(sl.ev, stream));
@@ -235,17 +248,24 @@ void upload_gemm(const GemmBatch& b, DevGemm& d) {
   d.ntiles = b.tiles.size();
   d.nsegs = b.segs.size();
   d.flops = b.flops;
+  d.tile = b.tile;
 }
 
 void launch_gemm_f64(const DevGemm& d, hipStream_t stream, int role) {
   for (size_t off = 0; off < d.ntiles; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(d.ntiles - off, (size_t)1 << 30);
-    if (role == 1)
-      hipLaunchKernelGGL(k_gemm_f64<1>, dim3(cnt), dim3(256), 0, stream, d.tiles + off, d.segs);
-    else if (role == 2)
-      hipLaunchKernelGGL(k_gemm_f64<2>, dim3(cnt), dim3(256), 0, stream, d.tiles + off, d.segs);
-    else
-      hipLaunchKernelGGL(k_gemm_f64<0>, dim3(cnt), dim3(256), 0, stream, d.tiles + off, d.segs);
+#define DMRG_LF(R, TM) \
+  hipLaunchKernelGGL((k_gemm_f64<R, TM>), dim3(cnt), dim3(64 * f64_waves(TM)), 0, stream, d.tiles + off, d.segs)
+    if (d.tile == 128) {
+      if (role == 1) DMRG_LF(1, 128);
+      else if (role == 2) DMRG_LF(2, 128);
+      else DMRG_LF(0, 128);
+    } else {
+      if (role == 1) DMRG_LF(1, 64);
+      else if (role == 2) DMRG_LF(2, 64);
+      else DMRG_LF(0, 64);
+    }
+#undef DMRG_LF
   }
   DMRG_HIP(hipGetLastError());
 }

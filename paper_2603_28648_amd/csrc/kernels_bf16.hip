@@ -62,11 +62,17 @@ constexpr int kFlush = 8;  // segments accumulated in FP32 between FP64 flushes
 // in FP32 only (its registers go to the larger block), with two LDS stages
 // (two workgroups per CU) or three (one slab more in flight, one workgroup
 // per CU in split-BF16x3).
+// The 256 x 256 tile (FP64 output only) runs eight waves as 2 x 4, each a
+// 128 x 64 block (four times the operand reuse per LDS byte of a 64 x 32
+// block), FP32 accumulation, two LDS stages of 64 KB: one workgroup per CU,
+// two waves per SIMD.
+constexpr int waves_of(int BM, int BN) { return (BM == 256 && BN == 256) ? 8 : 4; }
 template <int BM, int BN, int ST>
 struct TileCfg {
-  static constexpr bool ACC64 = !(BM == 128 && BN == 128);
+  static constexpr bool ACC64 = !(BM >= 128 && BN >= 128);
   static constexpr int STAGES = ST;
-  static constexpr int MIN_BLOCKS = (BM * BN <= 4096) ? 3 : (ST == 3 && !ACC64 ? 1 : 2);
+  static constexpr int WAVES = waves_of(BM, BN);
+  static constexpr int MIN_BLOCKS = (BM * BN <= 4096) ? 3 : ((ST == 3 && !ACC64) || WAVES == 8 ? 1 : 2);
 };
 
 __device__ __attribute__((aligned(16))) uint32_t g_zero16[4];  // 16 zero bytes (static storage)
@@ -96,9 +102,10 @@ struct SlabShape {
   static constexpr int NP = X3 ? 2 : 1;
   static constexpr int ROWS = NP * (BM + BN);    // 64-byte rows per slab
   static constexpr int BLOCKS = ROWS / 16;       // 1 KB load blocks per slab
-  static constexpr int PER_WAVE = BLOCKS / 4;    // load instructions per lane
+  static constexpr int WAVES = waves_of(BM, BN);
+  static constexpr int PER_WAVE = BLOCKS / WAVES;  // load instructions per lane
   static constexpr int ELEMS = ROWS * 32;        // bf16 per slab buffer
-  static_assert(BLOCKS % 4 == 0, "slab blocks split over four waves");
+  static_assert(BLOCKS % WAVES == 0, "slab blocks split over the waves");
 };
 
 // Per-lane sources of the slab loads: load j of a lane covers row
@@ -146,20 +153,23 @@ __device__ __forceinline__ bf16x8 frag(const uint16_t* part, int row, int q) {
 }
 
 template <bool X3, int OUT, int ROLE, int BM, int BN, int ST>
-__global__ __launch_bounds__(256, (TileCfg<BM, BN, ST>::MIN_BLOCKS)) void k_gemm_bf16(
+__global__ __launch_bounds__(64 * waves_of(BM, BN), (TileCfg<BM, BN, ST>::MIN_BLOCKS)) void k_gemm_bf16(
     const GemmTileB* __restrict__ tiles, const GemmSegB* __restrict__ segs) {
   using SS = SlabShape<X3, BM, BN>;
   using TC = TileCfg<BM, BN, ST>;
   constexpr int NP = SS::NP;
   constexpr int kStages = TC::STAGES;
-  constexpr int FM = BM / 32, FN = BN / 32;  // 16x16 blocks of a wave
+  constexpr int WV = TC::WAVES;
+  static_assert(WV == 4 || OUT == kOutF64, "eight-wave tiles write FP64 only");
+  // waves as 2 x 2 (or 2 x 4): each wave (BM / 2) x (BN / (WV / 2)) in 16x16 blocks
+  constexpr int FM = BM / 32, FN = BN / (8 * WV);
   constexpr int AM = TC::ACC64 ? FM : 1, AN = TC::ACC64 ? FN : 1;
   __shared__ __attribute__((aligned(16))) uint16_t smem[kStages][SS::ELEMS];
   const GemmTileB t = tiles[blockIdx.x];
   if (t.m <= 0) return;  // padding tile of the XCD-ordered launch
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * (BN / 2);
+  const int wm = (wave / (WV / 2)) * (BM / 2), wn = (wave % (WV / 2)) * (BN / (WV / 2));
   const int lr = lane & 15, lk = lane >> 4;
   double acc[AM][AN][4];  // FP64 accumulator (ACC64 shapes only)
   f32x4 sacc[FM][FN];
@@ -327,7 +337,7 @@ __global__ __launch_bounds__(256, (TileCfg<BM, BN, ST>::MIN_BLOCKS)) void k_gemm
         }
     __syncthreads();
     uint16_t* C = static_cast<uint16_t*>(t.c);
-    for (int c = tid; c < BM * BN / 8; c += 256) {
+    for (int c = tid; c < BM * BN / 8; c += 64 * WV) {
       const int i = c / (BN / 8), j = 8 * (c % (BN / 8));
       if (i >= t.m || j >= t.n) continue;
       const int64_t idx = ((int64_t)t.row0 + i) * t.ldc + (t.col0 + j);
@@ -354,11 +364,16 @@ DMRG_INST_SHAPE(64, 128, 3)
 DMRG_INST_SHAPE(128, 128, 2)
 DMRG_INST_SHAPE(128, 128, 3)
 #undef DMRG_INST_SHAPE
+template __global__ void k_gemm_bf16<true, kOutF64, 2, 256, 256, 2>(const GemmTileB*, const GemmSegB*);
+template __global__ void k_gemm_bf16<true, kOutF64, 0, 256, 256, 2>(const GemmTileB*, const GemmSegB*);
+template __global__ void k_gemm_bf16<false, kOutF64, 2, 256, 256, 2>(const GemmTileB*, const GemmSegB*);
+template __global__ void k_gemm_bf16<false, kOutF64, 0, 256, 256, 2>(const GemmTileB*, const GemmSegB*);
 
 template <int BM, int BN, int ST>
 static void launch_shape(const GemmTileB* tl, unsigned cnt, const GemmSegB* sg, bool x3, int out,
                          int role, hipStream_t s) {
-#define DMRG_LB(X, O, R) hipLaunchKernelGGL((k_gemm_bf16<X, O, R, BM, BN, ST>), dim3(cnt), dim3(256), 0, s, tl, sg)
+#define DMRG_LB(X, O, R) \
+  hipLaunchKernelGGL((k_gemm_bf16<X, O, R, BM, BN, ST>), dim3(cnt), dim3(64 * waves_of(BM, BN)), 0, s, tl, sg)
   if (x3) {
     if (out == kOutF64) { if (role == 2) DMRG_LB(true, kOutF64, 2); else DMRG_LB(true, kOutF64, 0); }
     else { if (role == 1) DMRG_LB(true, kOutBf16, 1); else DMRG_LB(true, kOutBf16, 0); }
@@ -376,6 +391,16 @@ void launch_gemm_bf16(const DevGemmB& d, bool x3, int out, int role, hipStream_t
     switch (d.shape) {
       case kShape128x128: launch_shape<128, 128, 2>(tl, cnt, d.segs, x3, out, role, s); break;
       case kShape128x128s3: launch_shape<128, 128, 3>(tl, cnt, d.segs, x3, out, role, s); break;
+      case kShape256x256:
+        DMRG_REQUIRE(out == kOutF64, kErrState, "gemm_bf16: the 256 x 256 tile writes FP64 only");
+        if (x3) {
+          if (role == 2) hipLaunchKernelGGL((k_gemm_bf16<true, kOutF64, 2, 256, 256, 2>), dim3(cnt), dim3(512), 0, s, tl, d.segs);
+          else hipLaunchKernelGGL((k_gemm_bf16<true, kOutF64, 0, 256, 256, 2>), dim3(cnt), dim3(512), 0, s, tl, d.segs);
+        } else {
+          if (role == 2) hipLaunchKernelGGL((k_gemm_bf16<false, kOutF64, 2, 256, 256, 2>), dim3(cnt), dim3(512), 0, s, tl, d.segs);
+          else hipLaunchKernelGGL((k_gemm_bf16<false, kOutF64, 0, 256, 256, 2>), dim3(cnt), dim3(512), 0, s, tl, d.segs);
+        }
+        break;
       case kShape64x64: launch_shape<64, 64, 3>(tl, cnt, d.segs, x3, out, role, s); break;
       case kShape64x128: launch_shape<64, 128, 3>(tl, cnt, d.segs, x3, out, role, s); break;
       default: launch_shape<128, 64, 3>(tl, cnt, d.segs, x3, out, role, s); break;
@@ -385,7 +410,7 @@ void launch_gemm_bf16(const DevGemmB& d, bool x3, int out, int role, hipStream_t
 }
 
 void upload_gemm_bf16(const GemmBatchB& b, DevGemmB& d) {
-  if (b.shape == kShape128x128 || b.shape == kShape128x128s3)  // FP32 accumulation: +-1 scales only
+  if (b.shape == kShape128x128 || b.shape == kShape128x128s3 || b.shape == kShape256x256)  // FP32 accumulation: +-1 scales only
     for (const GemmTileB& t : b.tiles)
       if (t.seg_end - t.seg_begin > 1)
         for (int k = t.seg_begin; k < t.seg_end; ++k)

@@ -35,7 +35,7 @@ BF_TOL = {"bf16": 1.6e-2, "bf16x3": 1.5e-4}
 @pytest.mark.parametrize("m,n,k", SHAPES)
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 @pytest.mark.parametrize("prec", ["bf16", "bf16x3"])
-@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4"])  # 128x64, 64x64, 64x128, 128x128 (2 or 3 LDS stages)
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4", "5"])  # 128x64, 64x64, 64x128, 128x128 (2 or 3 LDS stages), 256x256
 def test_gemm_bf16_matches_reference(ctx, monkeypatch, m, n, k, ta, tb, prec, tile):
     import torch
     monkeypatch.setenv("DMRG_BF16_SHAPE", tile)

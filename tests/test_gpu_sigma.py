@@ -75,8 +75,9 @@ def test_sigma_repeat_is_bitwise_deterministic(ctx):
 
 
 @pytest.mark.parametrize("K,N,tsz,D,i", [(8, 8, 0, 64, 3), (12, 12, 0, 256, 5), (10, 9, 1, 200, 2)])
-# 128x64, 64x64, 64x128, 128x128 (2 or 3 LDS stages), per problem, 128x128 with 64-wide edge tiles
-@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4", "5", "6"])
+# 128x64, 64x64, 64x128, 128x128 (2 or 3 LDS stages), 256x256 (stage 2), per problem, 128x128 with
+# 64-wide edge tiles
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4", "5", "6", "7"])
 def test_mixed_sigma_error_vs_fp64(ctx, monkeypatch, K, N, tsz, D, i, tile):
     """BF16 and split-BF16x3 sigma against the FP64 sigma of the same plan."""
     monkeypatch.setenv("DMRG_BF16_SHAPE", tile)
@@ -127,7 +128,7 @@ def test_autotuned_mixed_sigma(ctx, monkeypatch):
 BF16X3_FLOOR = 3e-6
 
 
-@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4", "5", "6"])
+@pytest.mark.parametrize("tile", ["0", "1", "2", "3", "4", "5", "6", "7"])
 def test_bf16x3_error_below_the_ladder_floor_for_every_tile(ctx, monkeypatch, tile):
     monkeypatch.setenv("DMRG_BF16_SHAPE", tile)
     print(f"bf16x3 error vs the ladder floor: K=14 D=300 window 6, tile {tile}", flush=True)
@@ -140,3 +141,19 @@ def test_bf16x3_error_below_the_ladder_floor_for_every_tile(ctx, monkeypatch, ti
     e48 = np.linalg.norm(s48 - s64) / np.linalg.norm(s64)
     print(f"  relative error {e48:.2e} (floor constant {BF16X3_FLOOR:.0e})", flush=True)
     assert e48 < BF16X3_FLOOR
+
+
+# FP64 sigma stages run on 64 x 64 (four waves) or 128 x 128 (eight waves)
+# tiles, chosen per stage (DMRG_F64_TILE); every combination against the oracle.
+@pytest.mark.parametrize("tiles", ["64,64", "128,128", "64,128", "128,64"])
+@pytest.mark.parametrize("K,N,tsz,D,i", [(12, 12, 0, 256, 5), (12, 14, 2, 150, 7)])
+def test_fp64_tiles_match_blocksparse_oracle(ctx, monkeypatch, tiles, K, N, tsz, D, i):
+    from oracle.blocksparse import BlockSparseSigma
+    monkeypatch.setenv("DMRG_F64_TILE", tiles)
+    print(f"FP64 tiles {tiles} vs oracle: K={K} N={N} 2Sz={tsz} D={D} window={i}", flush=True)
+    h, eri, m = case(K, N, tsz, D, i)
+    ref = BlockSparseSigma(m, h, eri).apply(m.psi)
+    got = lib_sigma(ctx, h, eri, m)
+    scale = max(float(np.max(np.abs(v))) for v in ref.values())
+    assert rel_err(got, ref) <= TOL
+    assert max_abs(got, ref) <= TOL * scale
