@@ -628,25 +628,38 @@ static std::vector<size_t> by_key(const AStage& A) {
 
 // FP64 descriptors of one stage (XCD-aware tile order).  Buffer `swap`
 // (if >= 0) is addressed at swap_ptr instead of its own storage.
-// Output tile of the FP64 sigma stages (stage 1, stage 2): measured at
-// CAS(54,36) D=4096, the 128 x 128 eight-wave tile is faster for stage 1
-// (309 against 355 ms per sigma) and the 64 x 64 four-wave tile for stage 2
-// (578 against 611 ms).  DMRG_F64_TILE="t1,t2" (64 or 128 each) overrides.
-static int f64_sigma_tile(int stage) {
-  int t[2] = {128, 64};
+// Output tile (rows, cols) of the FP64 sigma stages (stage 1, stage 2),
+// measured at CAS(54,36) D=4096 (ms per sigma, stage 1 / stage 2):
+// 128 x 128 for stage 1 (309 against 355 with 64 x 64); 128 x 64 with eight
+// waves for stage 2 (565, against 599 with 64 x 64, 586 with 64 x 128 and
+// 611 with 128 x 128, whose padding of narrow output blocks costs more than
+// its operand reuse gains).  DMRG_F64_TILE="t1,t2" overrides, each of 64,
+// 128 (square), 128x64 or 64x128.
+static std::pair<int, int> f64_sigma_tile(int stage) {
+  std::pair<int, int> t[2] = {{128, 128}, {128, 64}};
   if (const char* e = std::getenv("DMRG_F64_TILE")) {
-    DMRG_REQUIRE(std::sscanf(e, "%d,%d", &t[0], &t[1]) == 2 && (t[0] == 64 || t[0] == 128) &&
-                     (t[1] == 64 || t[1] == 128),
-                 kErrInvalidArg, "DMRG_F64_TILE must be \"t1,t2\" with 64 or 128 each");
+    auto parse = [](const std::string& w, std::pair<int, int>& o) {
+      int a = 0, b = 0;
+      if (std::sscanf(w.c_str(), "%dx%d", &a, &b) == 2) o = {a, b};
+      else if (std::sscanf(w.c_str(), "%d", &a) == 1) o = {a, a};
+      else return false;
+      return (o.first == 64 || o.first == 128) && (o.second == 64 || o.second == 128);
+    };
+    const std::string v(e);
+    const size_t comma = v.find(',');
+    DMRG_REQUIRE(comma != std::string::npos && parse(v.substr(0, comma), t[0]) && parse(v.substr(comma + 1), t[1]),
+                 kErrInvalidArg, "DMRG_F64_TILE must be \"t1,t2\", each 64, 128, 128x64 or 64x128");
   }
   return t[stage - 1];
 }
 
 static void materialize_f64(const std::vector<PlanBuf>& bufs, const AStage& A, DevGemm& out,
-                            int swap = -1, double* swap_ptr = nullptr, int tile = kTileM) {
+                            int swap = -1, double* swap_ptr = nullptr,
+                            std::pair<int, int> tile = {kTileM, kTileN}) {
   auto base = [&](int k) { return k == swap ? swap_ptr : bufs[k].f64; };
   GemmBatch b;
-  b.tile = tile;
+  b.tile = tile.first;
+  b.tile_n = tile.second;
   b.segs.reserve(A.segs.size());
   for (auto& g : A.segs)
     b.segs.push_back({base(g.a.buf) + g.a.off, base(g.b.buf) + g.b.off, g.lda, g.ldb, g.k, g.flags, g.alpha});

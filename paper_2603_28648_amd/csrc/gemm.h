@@ -44,19 +44,21 @@ struct GemmBatch {
   std::vector<GemmSeg> segs;
   std::vector<GemmTile> tiles;
   double flops = 0;  // algorithmic 2*m*n*k over all segments
-  int tile = kTileM;  // square output tile of the launch: 64 (4 waves) or 128 (8 waves)
+  // output tile of the launch (rows x cols): 64 x 64 (4 waves), 128 x 128,
+  // 128 x 64 or 64 x 128 (8 waves)
+  int tile = kTileM, tile_n = kTileN;
 
   // Adds one output problem C (m x n, ldc) += sum over segs [s0, s1).
-  // The problem is split into tile x tile pieces that share the segments.
+  // The problem is split into tile x tile_n pieces that share the segments.
   void add_problem(void* c, int ldc, int m, int n, size_t s0, size_t s1, int beta) {
     if (m <= 0 || n <= 0 || s1 <= s0) return;
     for (int r = 0; r < m; r += tile)
-      for (int q = 0; q < n; q += tile) {
+      for (int q = 0; q < n; q += tile_n) {
         GemmTile t;
         t.c = c;
         t.ldc = ldc;
         t.m = std::min(tile, m - r);
-        t.n = std::min(tile, n - q);
+        t.n = std::min(tile_n, n - q);
         t.row0 = r;
         t.col0 = q;
         t.seg_begin = (int32_t)s0;
@@ -148,7 +150,7 @@ struct DevGemm {
   GemmTile* tiles = nullptr;
   size_t ntiles = 0, nsegs = 0;
   double flops = 0;
-  int tile = kTileM;
+  int tile = kTileM, tile_n = kTileN;
 };
 void upload_gemm(const GemmBatch& b, DevGemm& d);
 void launch_gemm_f64(const DevGemm& d, hipStream_t stream, int role = 0);

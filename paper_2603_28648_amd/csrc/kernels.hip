@@ -14,9 +14,11 @@ namespace dmrg {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// One workgroup per TM x TM output tile: 64 x 64 with 4 waves (each a 32 x 32
-// quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64) or 128 x 128 with 8 waves
-// (each 64 x 32 as 4 x 2 blocks; twice the operand reuse per loaded byte).
+// One workgroup per TM x TN output tile: 64 x 64 with 4 waves (each a
+// 32 x 32 quarter as 2 x 2 blocks of v_mfma_f64_16x16x4f64), 128 x 128 with
+// 8 waves (each 64 x 32 as 4 x 2 blocks; twice the operand reuse per loaded
+// byte), or 128 x 64 / 64 x 128 with 8 waves of 32 x 32 (4/3 of the reuse at
+// the register count of the 64 x 64 tile).
 // Operands are staged through LDS in k-slabs of 16 with bounds-checked
 // (zero-filled) loads, so ragged m, n, k need no padding in memory.  alpha is
 // folded into A.  The slabs of all segments of a tile form one sequence,
@@ -28,25 +30,26 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // and B[l/16][l%16]; accumulator element v of lane l holds D[4*v + l/16][l%16]
 // (rows interleaved across the four 16-lane groups).
 constexpr int kTK = 16;
-constexpr int f64_waves(int TM) { return TM == 128 ? 8 : 4; }
+constexpr int f64_waves(int TM, int TN) { return TM == 64 && TN == 64 ? 4 : 8; }
+constexpr int f64_wave_rows(int TM, int TN) { return TM == 128 && TN == 64 ? 4 : 2; }
 
 // ROLE only names the kernel for profilers: 0 = operator construction,
 // 1 = sigma stage 1 (psi x right operator), 2 = sigma stage 2 (left operator x T).
-template <int ROLE, int TM>
-__global__ __launch_bounds__(64 * f64_waves(TM)) void k_gemm_f64(const GemmTile* __restrict__ tiles,
-                                                                 const GemmSeg* __restrict__ segs) {
-  constexpr int TN = TM;
-  constexpr int WV = f64_waves(TM), NT = 64 * WV;
-  constexpr int WC = WV / 2;                        // waves across the columns
-  constexpr int FM = TM / 32, FN = TN / (16 * WC);  // 16x16 blocks of a wave
+template <int ROLE, int TM, int TN>
+__global__ __launch_bounds__(64 * f64_waves(TM, TN)) void k_gemm_f64(const GemmTile* __restrict__ tiles,
+                                                                     const GemmSeg* __restrict__ segs) {
+  constexpr int WV = f64_waves(TM, TN), NT = 64 * WV;
+  constexpr int WR = f64_wave_rows(TM, TN), WC = WV / WR;  // waves down the rows / across the columns
+  constexpr int FM = TM / (16 * WR), FN = TN / (16 * WC);  // 16x16 blocks of a wave
   constexpr int kLoadsA = (TM * kTK) / NT, kLoadsB = (TN * kTK) / NT;
+  static_assert(FM >= 1 && FN >= 1 && kLoadsA >= 1 && kLoadsB >= 1, "k_gemm_f64: tile shape");
   __shared__ double As[2][kTK][TM + 1];
   __shared__ double Bs[2][kTK][TN + 1];
   const GemmTile t = tiles[blockIdx.x];
   if (t.m <= 0) return;  // padding tile of the XCD-ordered launch
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const int wm = (wave / WC) * (TM / 2), wn = (wave % WC) * (TN / WC);
+  const int wm = (wave / WC) * (TM / WR), wn = (wave % WC) * (TN / WC);
   const int lr = lane & 15, lk = lane >> 4;
   f64x4 acc[FM][FN];
 #pragma unroll
@@ -171,6 +174,28 @@ __global__ __launch_bounds__(64 * f64_waves(TM)) void k_gemm_f64(const GemmTile*
       }
 }
 
+// One launch of cnt tiles of the given shape (rows x cols) and role.
+static void launch_f64_tiles(int role, int tm, int tn, unsigned cnt, hipStream_t s, const GemmTile* tiles,
+                             const GemmSeg* segs) {
+#define DMRG_LF(R, TM, TN) \
+  hipLaunchKernelGGL((k_gemm_f64<R, TM, TN>), dim3(cnt), dim3(64 * f64_waves(TM, TN)), 0, s, tiles, segs)
+#define DMRG_LF_ROLES(TM, TN)           \
+  do {                                  \
+    if (role == 1) DMRG_LF(1, TM, TN);  \
+    else if (role == 2) DMRG_LF(2, TM, TN); \
+    else DMRG_LF(0, TM, TN);            \
+  } while (0)
+  if (tm == 128 && tn == 128) DMRG_LF_ROLES(128, 128);
+  else if (tm == 128 && tn == 64) DMRG_LF_ROLES(128, 64);
+  else if (tm == 64 && tn == 128) DMRG_LF_ROLES(64, 128);
+  else {
+    DMRG_REQUIRE(tm == 64 && tn == 64, kErrInvalidArg, "k_gemm_f64: tile must be 64x64, 128x128, 128x64 or 64x128");
+    DMRG_LF_ROLES(64, 64);
+  }
+#undef DMRG_LF_ROLES
+#undef DMRG_LF
+}
+
 // Descriptors of one-off launches go through a ring of pinned host buffers
 // copied asynchronously to device buffers, so that a launch needs no host
 // synchronisation: a slot is reused only after the event recorded behind
@@ -226,10 +251,7 @@ void launch_gemm_f64(const GemmBatch& b, hipStream_t stream) {
   const size_t nt = b.tiles.size();
   for (size_t off = 0; off < nt; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(nt - off, (size_t)1 << 30);
-    if (b.tile == 128)
-      hipLaunchKernelGGL((k_gemm_f64<0, 128>), dim3(cnt), dim3(512), 0, stream, dtiles + off, dsegs);
-    else
-      hipLaunchKernelGGL((k_gemm_f64<0, 64>), dim3(cnt), dim3(256), 0, stream, dtiles + off, dsegs);
+    launch_f64_tiles(0, b.tile, b.tile_n, cnt, stream, dtiles + off, dsegs);
   }
   DMRG_HIP(hipGetLastError());
   DMRG_HIP(hipEventRecord(sl.ev, stream));
@@ -249,23 +271,13 @@ void upload_gemm(const GemmBatch& b, DevGemm& d) {
   d.nsegs = b.segs.size();
   d.flops = b.flops;
   d.tile = b.tile;
+  d.tile_n = b.tile_n;
 }
 
 void launch_gemm_f64(const DevGemm& d, hipStream_t stream, int role) {
   for (size_t off = 0; off < d.ntiles; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(d.ntiles - off, (size_t)1 << 30);
-#define DMRG_LF(R, TM) \
-  hipLaunchKernelGGL((k_gemm_f64<R, TM>), dim3(cnt), dim3(64 * f64_waves(TM)), 0, stream, d.tiles + off, d.segs)
-    if (d.tile == 128) {
-      if (role == 1) DMRG_LF(1, 128);
-      else if (role == 2) DMRG_LF(2, 128);
-      else DMRG_LF(0, 128);
-    } else {
-      if (role == 1) DMRG_LF(1, 64);
-      else if (role == 2) DMRG_LF(2, 64);
-      else DMRG_LF(0, 64);
-    }
-#undef DMRG_LF
+    launch_f64_tiles(role, d.tile, d.tile_n, cnt, stream, d.tiles + off, d.segs);
   }
   DMRG_HIP(hipGetLastError());
 }

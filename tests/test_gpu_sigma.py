@@ -143,9 +143,10 @@ def test_bf16x3_error_below_the_ladder_floor_for_every_tile(ctx, monkeypatch, ti
     assert e48 < BF16X3_FLOOR
 
 
-# FP64 sigma stages run on 64 x 64 (four waves) or 128 x 128 (eight waves)
-# tiles, chosen per stage (DMRG_F64_TILE); every combination against the oracle.
-@pytest.mark.parametrize("tiles", ["64,64", "128,128", "64,128", "128,64"])
+# FP64 sigma stages run on 64 x 64 (four waves), 128 x 128, 128 x 64 or
+# 64 x 128 (eight waves) tiles, chosen per stage (DMRG_F64_TILE); each shape
+# in each stage against the oracle.
+@pytest.mark.parametrize("tiles", ["64,64", "128,128", "64,128", "128,64", "128x64,64x128", "64x128,128x64"])
 @pytest.mark.parametrize("K,N,tsz,D,i", [(12, 12, 0, 256, 5), (12, 14, 2, 150, 7)])
 def test_fp64_tiles_match_blocksparse_oracle(ctx, monkeypatch, tiles, K, N, tsz, D, i):
     from oracle.blocksparse import BlockSparseSigma
