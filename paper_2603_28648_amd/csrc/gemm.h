@@ -151,6 +151,7 @@ struct DevGemm {
   size_t ntiles = 0, nsegs = 0;
   double flops = 0;
   int tile = kTileM, tile_n = kTileN;
+  bool lds = false;  // every segment suits the direct-to-LDS kernel
 };
 void upload_gemm(const GemmBatch& b, DevGemm& d);
 void launch_gemm_f64(const DevGemm& d, hipStream_t stream, int role = 0);

@@ -1,6 +1,7 @@
 // gfx950 kernels: FP64-MFMA grouped GEMM and FP64 BLAS-1 helpers.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -174,16 +175,198 @@ __global__ __launch_bounds__(64 * f64_waves(TM, TN)) void k_gemm_f64(const GemmT
       }
 }
 
+// Direct-to-LDS variant for NT segments (A m x k and B stored n x k, both k
+// contiguous, with even leading dimensions and 16-byte aligned bases, so
+// that every 16-byte chunk of a row lies inside the row).  Each lane moves 16
+// bytes of a slab from global memory straight into LDS (global_load_lds): no
+// registers stage the operands, and a ring of three LDS stages keeps two
+// slabs in flight during the MFMAs of a third (two stages for 128 x 128, so
+// that two workgroups fit a CU).  A slab holds kTK = 16 k of
+// the TM rows of A and the TN rows of B, 128 bytes a row; chunk c (k 2c,
+// 2c + 1) of LDS row r sits at position c ^ ((r >> 1) & 7), so that the
+// fragment reads of 16 consecutive rows at one k (half a wave) meet each
+// bank once.  Chunks outside the operands read a zero buffer; k entries past
+// a segment's k that share a chunk with valid ones are zeroed in the
+// fragments, and alpha scales the A fragments.  The MFMA sequence (k-steps of
+// 4, segment by segment) is that of k_gemm_f64, so both give the same bits.
+__device__ __attribute__((aligned(16))) double g_f64_zero[2];  // 16 zero bytes (static storage)
+
+template <int N>
+__device__ __forceinline__ void f64_wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // gfx9 encoding of s_waitcnt: vmcnt low bits [3:0], high bits [15:14];
+  // expcnt and lgkmcnt at their maxima (not waited on)
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+__device__ __forceinline__ int f64_swz(int row) { return (row >> 1) & 7; }
+
+template <int ROLE, int TM, int TN>
+__global__ __launch_bounds__(64 * f64_waves(TM, TN)) void k_gemm_f64_lds(const GemmTile* __restrict__ tiles,
+                                                                         const GemmSeg* __restrict__ segs) {
+  constexpr int WV = f64_waves(TM, TN);
+  constexpr int WR = f64_wave_rows(TM, TN), WC = WV / WR;
+  constexpr int FM = TM / (16 * WR), FN = TN / (16 * WC);
+  constexpr int ROWS = TM + TN;        // 128-byte LDS rows of a slab
+  constexpr int NL = ROWS / (8 * WV);  // wave loads (8 rows each) per wave and slab
+  static_assert(NL >= 1 && NL * 8 * WV == ROWS && kTK == 16, "k_gemm_f64_lds: slab layout");
+  // three LDS stages where two workgroups still fit a CU, else two
+  constexpr int ST = 3 * ROWS * kTK * 8 <= 80 * 1024 ? 3 : 2;
+  __shared__ __attribute__((aligned(16))) double sm[ST][ROWS * kTK];
+  const GemmTile t = tiles[blockIdx.x];
+  if (t.m <= 0) return;  // padding tile of the XCD-ordered launch
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int wm = (wave / WC) * (TM / WR), wn = (wave % WC) * (TN / WC);
+  const int lr = lane & 15, lk = lane >> 4;
+  f64x4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  if (t.seg_begin < t.seg_end) {
+    // load j of a lane: LDS row 8 (wave NL + j) + lane / 8, position lane % 8
+    const double* src[NL];
+    int kc[NL];
+    auto segment = [&](const GemmSeg& g) {
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        const int r = 8 * (wave * NL + j) + (lane >> 3);
+        const int c = (lane & 7) ^ f64_swz(r);
+        kc[j] = 2 * c;
+        if (r < TM)
+          src[j] = r < t.m ? static_cast<const double*>(g.a) + (int64_t)(t.row0 + r) * g.lda + 2 * c : nullptr;
+        else
+          src[j] = r - TM < t.n ? static_cast<const double*>(g.b) + (int64_t)(t.col0 + r - TM) * g.ldb + 2 * c
+                                : nullptr;
+      }
+    };
+    int ps = t.seg_begin, pk0 = 0;
+    GemmSeg pg = segs[ps];
+    segment(pg);
+    int cs = ps, ck0 = 0;
+    GemmSeg cg = pg;
+    int issued = 0, done = 0;
+    auto produce = [&]() {
+      double* buf = &sm[issued % ST][0];
+#pragma unroll
+      for (int j = 0; j < NL; ++j) {
+        const double* p = (src[j] && pk0 + kc[j] < pg.k) ? src[j] + pk0 : g_f64_zero;
+        __builtin_amdgcn_global_load_lds(p, buf + 128 * (wave * NL + j), 16, 0, 0);
+      }
+      ++issued;
+      pk0 += kTK;
+      if (pk0 >= pg.k) {
+        pk0 = 0;
+        if (++ps < t.seg_end) {
+          pg = segs[ps];
+          segment(pg);
+        }
+      }
+    };
+    produce();
+    if (ST == 3 && ps < t.seg_end) produce();
+    while (cs < t.seg_end) {
+      // slab `done` is complete once at most ST - 2 newer slabs are pending
+      if (ST == 3 && issued > done + 1) f64_wait_vm<NL>();
+      else f64_wait_vm<0>();
+      // barrier without a memory fence: every wave's loads of this slab are
+      // in LDS, and every wave has read the buffer the next load overwrites
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+      if (ps < t.seg_end) produce();
+      const double* st = &sm[done % ST][0];
+      if (wm < t.m && wn < t.n) {
+        const int kv = cg.k - ck0;  // valid k of this slab
+#pragma unroll
+        for (int kk = 0; kk < kTK; kk += 4) {
+          if (kk >= kv) break;
+          const int k = kk + lk, c = k >> 1, h = k & 1;
+          double a[FM], b[FN];
+#pragma unroll
+          for (int i = 0; i < FM; ++i) {
+            const int r = wm + 16 * i + lr;
+            a[i] = st[r * kTK + 2 * (c ^ f64_swz(r)) + h];
+          }
+#pragma unroll
+          for (int j = 0; j < FN; ++j) {
+            const int r = TM + wn + 16 * j + lr;
+            b[j] = st[r * kTK + 2 * (c ^ f64_swz(r)) + h];
+          }
+          if (kv - kk < 4) {  // the segment's last k-step: entries past k are zero
+            const bool ok = k < kv;
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[i] = ok ? a[i] : 0.0;
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = ok ? b[j] : 0.0;
+          }
+#pragma unroll
+          for (int i = 0; i < FM; ++i) a[i] *= cg.alpha;
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+            if (wm + 16 * i < t.m)
+#pragma unroll
+              for (int j = 0; j < FN; ++j)
+                if (wn + 16 * j < t.n)
+                  acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      ++done;
+      ck0 += kTK;
+      if (ck0 >= cg.k) {
+        ck0 = 0;
+        if (++cs < t.seg_end) cg = segs[cs];
+      }
+    }
+  }
+  double* __restrict__ C = static_cast<double*>(t.c);
+#pragma unroll
+  for (int bi = 0; bi < FM; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < FN; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wm + bi * 16 + 4 * v + lk;
+        const int j = wn + bj * 16 + lr;
+        if (i < t.m && j < t.n) {
+          double* p = C + ((int64_t)t.row0 + i) * t.ldc + (t.col0 + j);
+          const double val = acc[bi][bj][v];
+          *p = t.beta ? (*p + val) : val;
+        }
+      }
+}
+
+// Whether every segment of a launch suits k_gemm_f64_lds: NT operands with
+// even leading dimensions and 16-byte aligned bases.  DMRG_F64_LDS=0 keeps
+// every launch on k_gemm_f64.
+static bool f64_lds_ok(const GemmSeg* segs, size_t n) {
+  const char* e = std::getenv("DMRG_F64_LDS");
+  if (e && std::atoi(e) == 0) return false;
+  for (size_t i = 0; i < n; ++i) {
+    const GemmSeg& g = segs[i];
+    if ((g.flags & kTransA) || !(g.flags & kTransB) || (g.lda & 1) || (g.ldb & 1) ||
+        (reinterpret_cast<uintptr_t>(g.a) & 15) || (reinterpret_cast<uintptr_t>(g.b) & 15))
+      return false;
+  }
+  return true;
+}
+
 // One launch of cnt tiles of the given shape (rows x cols) and role.
-static void launch_f64_tiles(int role, int tm, int tn, unsigned cnt, hipStream_t s, const GemmTile* tiles,
+static void launch_f64_tiles(int role, int tm, int tn, bool lds, unsigned cnt, hipStream_t s, const GemmTile* tiles,
                              const GemmSeg* segs) {
-#define DMRG_LF(R, TM, TN) \
-  hipLaunchKernelGGL((k_gemm_f64<R, TM, TN>), dim3(cnt), dim3(64 * f64_waves(TM, TN)), 0, s, tiles, segs)
-#define DMRG_LF_ROLES(TM, TN)           \
-  do {                                  \
-    if (role == 1) DMRG_LF(1, TM, TN);  \
+#define DMRG_LF(R, TM, TN)                                                                                       \
+  do {                                                                                                          \
+    if (lds)                                                                                                    \
+      hipLaunchKernelGGL((k_gemm_f64_lds<R, TM, TN>), dim3(cnt), dim3(64 * f64_waves(TM, TN)), 0, s, tiles, segs); \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_gemm_f64<R, TM, TN>), dim3(cnt), dim3(64 * f64_waves(TM, TN)), 0, s, tiles, segs);     \
+  } while (0)
+#define DMRG_LF_ROLES(TM, TN)               \
+  do {                                      \
+    if (role == 1) DMRG_LF(1, TM, TN);      \
     else if (role == 2) DMRG_LF(2, TM, TN); \
-    else DMRG_LF(0, TM, TN);            \
+    else DMRG_LF(0, TM, TN);                \
   } while (0)
   if (tm == 128 && tn == 128) DMRG_LF_ROLES(128, 128);
   else if (tm == 128 && tn == 64) DMRG_LF_ROLES(128, 64);
@@ -249,9 +432,10 @@ void launch_gemm_f64(const GemmBatch& b, hipStream_t stream) {
   GemmSeg* dsegs = sl.dev.as<GemmSeg>();
   GemmTile* dtiles = reinterpret_cast<GemmTile*>(sl.dev.as<char>() + sba);
   const size_t nt = b.tiles.size();
+  const bool lds = f64_lds_ok(b.segs.data(), b.segs.size());
   for (size_t off = 0; off < nt; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(nt - off, (size_t)1 << 30);
-    launch_f64_tiles(0, b.tile, b.tile_n, cnt, stream, dtiles + off, dsegs);
+    launch_f64_tiles(0, b.tile, b.tile_n, lds, cnt, stream, dtiles + off, dsegs);
   }
   DMRG_HIP(hipGetLastError());
   DMRG_HIP(hipEventRecord(sl.ev, stream));
@@ -272,12 +456,13 @@ void upload_gemm(const GemmBatch& b, DevGemm& d) {
   d.flops = b.flops;
   d.tile = b.tile;
   d.tile_n = b.tile_n;
+  d.lds = f64_lds_ok(b.segs.data(), b.segs.size());
 }
 
 void launch_gemm_f64(const DevGemm& d, hipStream_t stream, int role) {
   for (size_t off = 0; off < d.ntiles; off += (size_t)1 << 30) {
     const unsigned cnt = (unsigned)std::min<size_t>(d.ntiles - off, (size_t)1 << 30);
-    launch_f64_tiles(role, d.tile, d.tile_n, cnt, stream, d.tiles + off, d.segs);
+    launch_f64_tiles(role, d.tile, d.tile_n, d.lds, cnt, stream, d.tiles + off, d.segs);
   }
   DMRG_HIP(hipGetLastError());
 }

@@ -158,3 +158,25 @@ def test_fp64_tiles_match_blocksparse_oracle(ctx, monkeypatch, tiles, K, N, tsz,
     scale = max(float(np.max(np.abs(v))) for v in ref.values())
     assert rel_err(got, ref) <= TOL
     assert max_abs(got, ref) <= TOL * scale
+
+
+# The FP64 stages run on a direct-to-LDS kernel when every segment of a launch
+# has NT operands with even leading dimensions and 16-byte aligned bases
+# (else, or with DMRG_F64_LDS=0, on the register-staged kernel).  Both issue
+# the same MFMA sequence, so the sigma must agree bit for bit, for each tile
+# shape.
+@pytest.mark.parametrize("tiles", ["128,128x64", "64,64", "64x128,128"])
+@pytest.mark.parametrize("K,N,tsz,D,i", [(12, 12, 0, 256, 5), (10, 9, 1, 200, 2)])
+def test_fp64_lds_kernel_is_bitwise_the_register_kernel(ctx, monkeypatch, tiles, K, N, tsz, D, i):
+    monkeypatch.setenv("DMRG_F64_TILE", tiles)
+    print(f"FP64 direct-to-LDS vs register-staged kernel, tiles {tiles}: K={K} D={D} window={i}", flush=True)
+    h, eri, m = case(K, N, tsz, D, i)
+    x = None
+    out = {}
+    for lds in ("1", "0"):
+        monkeypatch.setenv("DMRG_F64_LDS", lds)
+        n = lib_load(ctx, h, eri, m)
+        if x is None:
+            x = np.random.default_rng(8).normal(size=n)
+        out[lds] = lib_sigma_flat(ctx, x, "fp64")
+    assert np.array_equal(out["1"], out["0"])
