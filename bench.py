@@ -258,9 +258,9 @@ def main():
         t64, kt64, _ = timed_sigma("fp64", args.fp64_steps, 0, ref, True)
         fp64 = {"ms": float(np.median(t64)), "tflops": info["flops"] / (np.median(t64) * 1e-3) / 1e12}
         fp64["frac_of_fp64_peak"] = fp64["tflops"] / PEAK_TFLOPS["fp64"]
-        fp64["roofline"] = kernel_roofline(kt64, "k_gemm_f64", PEAK_TFLOPS["fp64"], "TFLOP/s", 1.0)
+        fp64["roofline"] = kernel_roofline(kt64, "k_gemm_f64_lds", PEAK_TFLOPS["fp64"], "TFLOP/s", 1.0)
         log(f"[bench] sigma fp64: median {fp64['ms']:.2f} ms ({fp64['tflops']:.2f} TFLOP/s); "
-            f"k_gemm_f64 {fp64['roofline']['achieved']:.1f} TFLOP/s per launch")
+            f"k_gemm_f64_lds {fp64['roofline']['achieved']:.1f} TFLOP/s per launch")
     times, _, t_wall = timed_sigma(args.precision, args.steps, args.warmup, out, False)
     ms = float(np.median(times))
     # per-kernel times for the roofline: a few more steps with the timing hook
@@ -283,7 +283,7 @@ def main():
     ms_kernel = (kt["ms_stage1"] + kt["ms_stage2"]) / max(1, n_launch)
     flops_launch = (kt["flops_stage1"] + kt["flops_stage2"]) * kt["calls"] / max(1, n_launch)
     achieved = flops_launch / (ms_kernel * 1e-3) / 1e12
-    kname = "k_gemm_f64" if args.precision == "fp64" else "k_gemm_bf16"
+    kname = "k_gemm_f64_lds" if args.precision == "fp64" else "k_gemm_bf16"
     log(f"[bench] {kname}: {n_launch} launches, avg {ms_kernel:.3f} ms, stage1 "
         f"{kt['ms_stage1'] / kt['calls']:.1f} ms + stage2 {kt['ms_stage2'] / kt['calls']:.1f} ms + "
         f"pinned FP64 {kt['ms_pinned'] / kt['calls']:.1f} ms per sigma; {achieved:.1f} TFLOP/s")
