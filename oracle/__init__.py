@@ -18,6 +18,10 @@ blocksparse renormalised block operators, the normal/complementary sigma and
 truncation  the two-site truncation (per-sector SVD, global selection of the
             D largest weights, truncation error) and the window move.
 orbital     generalised Fock matrix and orbital gradient from the RDMs.
+su2         spin adaptation: Clebsch-Gordan and 6j coefficients, multiplet
+            bases of blocks, the spin-adapted window H_eff (plain
+            definition) and the scalar-product recoupling rule of a
+            spin-adapted sigma.
 
 Every function is pinned by tests under tests/ (test_oracle_*.py) against
 closed forms, brute force or the plain definitions; the pins are listed in

@@ -1,0 +1,236 @@
+"""Spin adaptation (SU(2)) of the two-site window -- TEST INFRASTRUCTURE ONLY.
+
+The paper's production runs use spin-adapted DMRG (bond dimensions counted in
+multiplets, D_SU(2); Numerical procedure section, Fig. 2-3).  This module
+holds the plain definitions that a spin-adapted sigma has to reproduce:
+
+* Spins are passed doubled (tj = 2j), so that half-integers stay integers.
+* clebsch_gordan(tj1, tm1, tj2, tm2, tJ, tM) = <j1 m1; j2 m2 | J M>, Racah's
+  closed formula with the Condon-Shortley phase (<j1 j1; j2 J-j1 | J J> > 0).
+* wigner_6j(tj1, tj2, tj3, tj4, tj5, tj6) = {j1 j2 j3; j4 j5 j6}, Racah's
+  closed formula (a sum over one index of factorial ratios).
+* Multiplet bases of a block of orbitals: for every particle number N and
+  spin S, the highest-weight states (S_z = S, S_+ psi = 0) span the
+  multiplets; the other components follow by the lowering operator,
+  |S M-1> = S_- |S M> / sqrt(S(S+1) - M(M-1)) (the Condon-Shortley
+  convention).  `multiplets(n_orb, rng=None, keep=None)` builds them for a
+  block's Fock space, all of them or a random subset of each (N, S).
+* Reduced matrix elements, with the convention of the Wigner-Eckart theorem
+  written with a Clebsch-Gordan coefficient:
+      <a' S' M'| T^k_q |a S M> = <S M; k q | S' M'> <a' S' || T^k || a S>.
+* The coupled basis of two blocks (left orbitals first in the Jordan-Wigner
+  order, so a product of block states is the concatenated determinant with
+  no sign): |(a S_a, b S_b) S M> = sum <S_a M_a; S_b M_b | S M> |a M_a>|b M_b>.
+* heff_su2: the spin-adapted effective Hamiltonian of the window, the plain
+  definition <c'| H |c> over coupled states c of total spin S at one M (the
+  reduced matrix does not depend on M).
+* scalar_coupling: the matrix element of the scalar product
+  [A^k x B^k]^0 = sum_q <k q; k -q | 0 0> A_q B_-q between coupled states,
+  for unit reduced elements of A (left block) and B (right block), without
+  the fermion sign (-1)^(p(B) N_a):
+      (-1)^(S_a + S_b' + S + k) sqrt((2 S_a' + 1)(2 S_b' + 1) / (2k + 1))
+          {S_a S_b S; S_b' S_a' k}.
+  A spin-adapted sigma is a sum of such scalar products of left and right
+  (enlarged-block) tensor operators of rank 0, 1/2 and 1, each a product of
+  reduced block matrices weighted by this coefficient, which is what the
+  grouped block GEMMs would execute.
+
+Pins (tests/test_oracle_su2.py): Clebsch-Gordan orthonormality, the closed
+form for j2 = 1/2 and the eigenvectors of J^2 built from explicit spin
+matrices; the 6j orthogonality relation and the special value with a zero
+entry; scalar_coupling against the explicit Clebsch-Gordan sum that defines
+it; multiplet bases against S^2, S_+ and the sector dimensions; heff_su2 at
+complete bases against the full-CI eigenvalues of spin S (states of the
+(N, 2S_z = 2S) sector with <S^2> = S(S+1), from oracle.fock), and at two
+values of M; the scalar-product rule (with fermion signs) against the
+operator built component by component on the Fock space.
+"""
+from math import factorial, sqrt
+
+import numpy as np
+
+from .fock import DetSpace
+
+
+# ---- angular momentum algebra (doubled spins) --------------------------------
+def _f(t2):
+    """factorial of t2 / 2 (t2 even, >= 0)."""
+    assert t2 % 2 == 0 and t2 >= 0, t2
+    return factorial(t2 // 2)
+
+
+def _triangle(ta, tb, tc):
+    return abs(ta - tb) <= tc <= ta + tb and (ta + tb + tc) % 2 == 0
+
+
+def clebsch_gordan(tj1, tm1, tj2, tm2, tJ, tM):
+    """<j1 m1; j2 m2 | J M> (arguments doubled), Racah's formula."""
+    if tm1 + tm2 != tM or not _triangle(tj1, tj2, tJ):
+        return 0.0
+    if abs(tm1) > tj1 or abs(tm2) > tj2 or abs(tM) > tJ:
+        return 0.0
+    if (tj1 + tm1) % 2 or (tj2 + tm2) % 2 or (tJ + tM) % 2:
+        return 0.0
+    pre = (tJ + 1) * _f(tJ + tj1 - tj2) * _f(tJ - tj1 + tj2) * _f(tj1 + tj2 - tJ) / _f(tj1 + tj2 + tJ + 2)
+    pre *= _f(tJ + tM) * _f(tJ - tM) * _f(tj1 - tm1) * _f(tj1 + tm1) * _f(tj2 - tm2) * _f(tj2 + tm2)
+    s = 0.0
+    for k in range(0, (tj1 + tj2 + tJ) // 2 + 1):
+        d = (2 * k, tj1 + tj2 - tJ - 2 * k, tj1 - tm1 - 2 * k, tj2 + tm2 - 2 * k,
+             tJ - tj2 + tm1 + 2 * k, tJ - tj1 - tm2 + 2 * k)
+        if min(d) < 0:
+            continue
+        den = 1
+        for x in d:
+            den *= _f(x)
+        s += (-1) ** k / den
+    return sqrt(pre) * s
+
+
+def _delta(ta, tb, tc):
+    return sqrt(_f(ta + tb - tc) * _f(ta - tb + tc) * _f(-ta + tb + tc) / _f(ta + tb + tc + 2))
+
+
+def wigner_6j(tj1, tj2, tj3, tj4, tj5, tj6):
+    """{j1 j2 j3; j4 j5 j6} (arguments doubled), Racah's formula."""
+    if not (_triangle(tj1, tj2, tj3) and _triangle(tj1, tj5, tj6) and _triangle(tj4, tj2, tj6)
+            and _triangle(tj4, tj5, tj3)):
+        return 0.0
+    pre = _delta(tj1, tj2, tj3) * _delta(tj1, tj5, tj6) * _delta(tj4, tj2, tj6) * _delta(tj4, tj5, tj3)
+    lo = max(tj1 + tj2 + tj3, tj1 + tj5 + tj6, tj4 + tj2 + tj6, tj4 + tj5 + tj3)
+    hi = min(tj1 + tj2 + tj4 + tj5, tj2 + tj3 + tj5 + tj6, tj3 + tj1 + tj6 + tj4)
+    s = 0.0
+    for t2 in range(lo, hi + 1, 2):
+        den = (_f(t2 - tj1 - tj2 - tj3) * _f(t2 - tj1 - tj5 - tj6) * _f(t2 - tj4 - tj2 - tj6)
+               * _f(t2 - tj4 - tj5 - tj3) * _f(tj1 + tj2 + tj4 + tj5 - t2)
+               * _f(tj2 + tj3 + tj5 + tj6 - t2) * _f(tj3 + tj1 + tj6 + tj4 - t2))
+        s += (-1) ** (t2 // 2) * _f(t2 + 2) / den
+    return pre * s
+
+
+def scalar_coupling(tSa2, tSb2, tSa, tSb, tS, tk):
+    """<(a' S_a', b' S_b') S M | [A^k x B^k]^0 | (a S_a, b S_b) S M> for unit
+    reduced elements, without the fermion sign (closed form in the module
+    docstring; primed spins first)."""
+    ph = (tSa + tSb2 + tS + tk) // 2
+    return (-1) ** ph * sqrt((tSa2 + 1) * (tSb2 + 1) / (tk + 1)) * wigner_6j(tSa, tSb, tS, tSb2, tSa2, tk)
+
+
+# ---- multiplet bases of a block of orbitals ----------------------------------
+def _sector(n_orb, n, t2m):
+    try:
+        return DetSpace.sector(n_orb, n, t2m)
+    except ValueError:
+        return None
+
+
+def _s_plus(space_from, space_to):
+    """S_+ = sum_i a+_{i up} a_{i dn} from (N, 2M) to (N, 2M + 2) (dense)."""
+    m = np.zeros((space_to.dim, space_from.dim))
+    for i in range(space_from.K):
+        m += space_from.string_matrix([(2 * i, True), (2 * i + 1, False)], space_to).toarray()
+    return m
+
+
+class Multiplet:
+    """The multiplets of one (N, S) of a block: vec[tM] is the (sector dim x
+    D) matrix whose column alpha is the state |alpha S M> in the block's
+    (N, 2M) determinant sector space[tM]."""
+
+    def __init__(self, n, tS, space, vec):
+        self.n, self.tS, self.space, self.vec = n, tS, space, vec
+
+    @property
+    def dim(self):
+        return next(iter(self.vec.values())).shape[1]
+
+
+def multiplets(n_orb, rng=None, keep=None):
+    """All multiplets of a block of n_orb orbitals, by (N, S): the
+    highest-weight states of each (N, 2S_z = 2S) sector (null space of S_+),
+    then lowered.  With rng and keep, only min(keep, count) random orthonormal
+    combinations of each (N, S) are kept (a truncated spin-adapted basis)."""
+    out = []
+    for n in range(0, 2 * n_orb + 1):
+        for tS in range(n % 2, min(n, 2 * n_orb - n) + 1, 2):
+            top = _sector(n_orb, n, tS)
+            if top is None:
+                continue
+            up = _sector(n_orb, n, tS + 2)
+            if up is None:
+                hw = np.eye(top.dim)
+            else:
+                sp_ = _s_plus(top, up)
+                u, sv, vt = np.linalg.svd(sp_)
+                rank = int(np.sum(sv > 1e-10))
+                hw = vt[rank:].T
+            if hw.shape[1] == 0:
+                continue
+            if rng is not None and keep is not None:
+                q, _ = np.linalg.qr(rng.normal(size=(hw.shape[1], hw.shape[1])))
+                hw = hw @ q[:, :min(keep, hw.shape[1])]
+            vec, space = {tS: hw}, {tS: top}
+            cur, tM = hw, tS
+            while tM > -tS:
+                lower = _sector(n_orb, n, tM - 2)
+                smin = _s_plus(lower, space[tM]).T  # S_- = S_+^T
+                norm = sqrt((tS / 2) * (tS / 2 + 1) - (tM / 2) * (tM / 2 - 1))
+                cur = smin @ cur / norm
+                tM -= 2
+                vec[tM], space[tM] = cur, lower
+            out.append(Multiplet(n, tS, space, vec))
+    return out
+
+
+# ---- coupled states of two blocks and the spin-adapted H_eff -----------------
+def coupled_basis(left, right, n, tS):
+    """The coupled states (a, alpha, b, beta) of total N = n and spin S."""
+    out = []
+    for ia, A in enumerate(left):
+        for ib, B in enumerate(right):
+            if A.n + B.n != n or not _triangle(A.tS, B.tS, tS):
+                continue
+            for al in range(A.dim):
+                for be in range(B.dim):
+                    out.append((ia, al, ib, be))
+    return out
+
+
+def coupled_vectors(left, right, n_left, n_right, n, tS, tM, basis):
+    """Fock vectors (columns) of the coupled states in the (n, 2M) sector of
+    the n_left + n_right orbitals: sum_{M_a+M_b=M} CG |a M_a> |b M_b>, the
+    left determinant in the low bits."""
+    space = DetSpace.sector(n_left + n_right, n, tM)
+    P = np.zeros((space.dim, len(basis)))
+    shift = np.int64(2 * n_left)
+    for c, (ia, al, ib, be) in enumerate(basis):
+        A, B = left[ia], right[ib]
+        for tMa in range(-A.tS, A.tS + 1, 2):
+            tMb = tM - tMa
+            if abs(tMb) > B.tS:
+                continue
+            cg = clebsch_gordan(A.tS, tMa, B.tS, tMb, tS, tM)
+            if cg == 0.0:
+                continue
+            va, vb = A.vec[tMa][:, al], B.vec[tMb][:, be]
+            da, db = A.space[tMa].dets, B.space[tMb].dets
+            full = (da[:, None] | (db[None, :] << shift)).ravel()
+            amp = (va[:, None] * vb[None, :]).ravel()
+            P[space.index(full), c] += cg * amp
+    return P, space
+
+
+def heff_su2(h, eri, left, right, n_left, n_right, n, tS, tM=None):
+    """The spin-adapted effective Hamiltonian <c'|H|c> over the coupled states
+    of total spin S (at M = tM / 2, default S): the plain definition.
+    Returns (matrix, basis)."""
+    tM = tS if tM is None else tM
+    basis = coupled_basis(left, right, n, tS)
+    P, space = coupled_vectors(left, right, n_left, n_right, n, tS, tM, basis)
+    H = space.hamiltonian(h, eri).toarray()
+    return P.T @ H @ P, basis
+
+
+def sigma_su2(h, eri, left, right, n_left, n_right, n, tS, psi):
+    """H_eff psi for the reduced (spin-adapted) window vector psi."""
+    m, _ = heff_su2(h, eri, left, right, n_left, n_right, n, tS)
+    return m @ psi
