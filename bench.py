@@ -47,13 +47,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def profiled_traffic(sources, config):
-    """HBM bytes per sigma of the BF16 grouped GEMM from the committed
-    rocprofv3 summary, if it was taken with these sources (the kernel and the
-    schedule that builds its launches) and launch configuration (else None)."""
+def profiled_traffic(profile, sources, key, config):
+    """HBM bytes per sigma of a grouped-GEMM family from a committed rocprofv3
+    summary under profiles/, if it was taken with these sources (the kernel
+    and the schedule that builds its launches) and this launch configuration
+    (the value of the `key:` line), else None.  Returns (bytes per sigma,
+    launches per sigma)."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "k_gemm_bf16_sigma_cas54_36_D4096.md")
+    path = os.path.join(ROOT, "profiles", profile)
     try:
         text = open(path).read()
         h = hashlib.sha256()
@@ -63,12 +65,12 @@ def profiled_traffic(sources, config):
     except OSError:
         return None
     m_sha = re.search(r"sources_sha256:\s*([0-9a-f]+)", text)
-    m_cfg = re.search(r"bf16_launch_config:\s*(\d+),(\d+)", text)
+    m_cfg = re.search(re.escape(key) + r":\s*(\S+)", text)
     m_tr = re.search(r"traffic_bytes_per_sigma:\s*([0-9.eE+]+)", text)
     m_ln = re.search(r"launches_per_sigma:\s*(\d+)", text)
     if not (m_sha and m_cfg and m_tr and m_ln) or m_sha.group(1) != sha:
         return None
-    if (int(m_cfg.group(1)), int(m_cfg.group(2))) != tuple(config):
+    if m_cfg.group(1) != config:
         return None
     return float(m_tr.group(1)), int(m_ln.group(1))
 
@@ -259,6 +261,16 @@ def main():
         fp64 = {"ms": float(np.median(t64)), "tflops": info["flops"] / (np.median(t64) * 1e-3) / 1e12}
         fp64["frac_of_fp64_peak"] = fp64["tflops"] / PEAK_TFLOPS["fp64"]
         fp64["roofline"] = kernel_roofline(kt64, "k_gemm_f64_lds", PEAK_TFLOPS["fp64"], "TFLOP/s", 1.0)
+        # HBM bytes per launch from the committed FP64 profile (default tiles,
+        # direct-to-LDS kernel, same kernel and schedule sources), else None
+        fp64["roofline"]["traffic"] = None
+        if args.config == "cas54_36" and os.environ.get("DMRG_F64_LDS", "1") != "0":
+            csrc = os.path.join(ROOT, "paper_2603_28648_amd", "csrc")
+            pt = profiled_traffic("k_gemm_f64_sigma_cas54_36_D4096.md",
+                                  [os.path.join(csrc, "kernels.hip"), os.path.join(csrc, "engine.cpp")],
+                                  "fp64_tiles", os.environ.get("DMRG_F64_TILE", "128,128x64"))
+            if pt is not None:
+                fp64["roofline"]["traffic"] = pt[0] / pt[1]
         log(f"[bench] sigma fp64: median {fp64['ms']:.2f} ms ({fp64['tflops']:.2f} TFLOP/s); "
             f"k_gemm_f64_lds {fp64['roofline']['achieved']:.1f} TFLOP/s per launch")
     times, _, t_wall = timed_sigma(args.precision, args.steps, args.warmup, out, False)
@@ -389,8 +401,9 @@ def main():
     traffic = None
     if args.precision != "fp64" and args.config == "cas54_36":
         csrc = os.path.join(ROOT, "paper_2603_28648_amd", "csrc")
-        pt = profiled_traffic([os.path.join(csrc, "kernels_bf16.hip"), os.path.join(csrc, "engine.cpp")],
-                              (tuned["stage1"], tuned["stage2"]))
+        pt = profiled_traffic("k_gemm_bf16_sigma_cas54_36_D4096.md",
+                              [os.path.join(csrc, "kernels_bf16.hip"), os.path.join(csrc, "engine.cpp")],
+                              "bf16_launch_config", f"{tuned['stage1']},{tuned['stage2']}")
         if pt is not None:
             traffic = pt[0] / pt[1]  # bytes per chunk-stage launch
     log(f"[bench] HBM traffic per launch from the committed profile: "
@@ -419,6 +432,8 @@ def main():
                    "sigma_rel_err_vs_fp64": rel,
                    "fp64_sigma_ms": fp64["ms"] if fp64 else None,
                    "fp64_sigma_tflops": fp64["tflops"] if fp64 else None,
+                   "fp64_frac_of_peak": fp64["frac_of_fp64_peak"] if fp64 else None,
+                   "fp64_roofline": fp64["roofline"] if fp64 else None,
                    "speedup_vs_fp64": fp64["ms"] / ms if fp64 else None,
                    "bf16_launch_config": tuned if args.precision != "fp64" else None,
                    "graphs": not args.no_graphs,
