@@ -234,3 +234,36 @@ def sigma_su2(h, eri, left, right, n_left, n_right, n, tS, psi):
     """H_eff psi for the reduced (spin-adapted) window vector psi."""
     m, _ = heff_su2(h, eri, left, right, n_left, n_right, n, tS)
     return m @ psi
+
+
+# ---- the spin-adapted contraction ------------------------------------------
+def coupled_blocks(left_sectors, right_sectors, n, tS):
+    """The blocks (ia, ib) of a spin-adapted window vector: left sector ia =
+    (N_a, 2S_a, d_a) and right sector ib with N_a + N_b = n and S in
+    S_a x S_b; each block is a d_a x d_b matrix."""
+    return [(ia, ib) for ia, (na, tsa, _) in enumerate(left_sectors)
+            for ib, (nb, tsb, _) in enumerate(right_sectors)
+            if na + nb == n and _triangle(tsa, tsb, tS)]
+
+
+def contract_scalar_products(left_sectors, right_sectors, n, tS, psi, pairs):
+    """sigma = sum over pairs (c, tk, parity_b, A, B) of c [A^k x B^k]^0 psi on
+    the coupled blocks: A maps left sectors (blocks A[(ia2, ia)] of reduced
+    matrix elements), B right sectors, psi and the result are dicts
+    {(ia, ib): d_a x d_b matrix}.  Block by block:
+        sigma[ia2, ib2] += c (-1)^(parity_b N_a) scalar_coupling(...)
+                           A[ia2, ia] psi[ia, ib] B[ib2, ib]^T."""
+    blocks = set(coupled_blocks(left_sectors, right_sectors, n, tS))
+    out = {k: np.zeros((left_sectors[k[0]][2], right_sectors[k[1]][2])) for k in blocks}
+    for c, tk, pb, A, B in pairs:
+        for (ia2, ia), a in A.items():
+            for (ib2, ib), b in B.items():
+                if (ia, ib) not in blocks or (ia2, ib2) not in blocks:
+                    continue
+                coef = scalar_coupling(left_sectors[ia2][1], right_sectors[ib2][1], left_sectors[ia][1],
+                                       right_sectors[ib][1], tS, tk)
+                if coef == 0.0:
+                    continue
+                sign = -1.0 if (pb and left_sectors[ia][0] % 2) else 1.0
+                out[(ia2, ib2)] += c * sign * coef * (a @ psi[(ia, ib)] @ b.T)
+    return out

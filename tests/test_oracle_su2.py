@@ -259,3 +259,38 @@ def test_scalar_product_rule_against_the_fock_space_operator(dn, tk):
             rule[c2, c] = ((-1) ** (pb * left[ia].n)) * coef * ta[(ia2, ia)][al2, al] * tb[(ib2, ib)][be2, be]
     assert np.abs(brute).max() > 1e-3
     assert np.allclose(rule, brute, atol=1e-11)
+
+
+def test_contract_scalar_products_against_the_fock_space_operators():
+    """The block-by-block spin-adapted contraction (the rule a spin-adapted
+    sigma runs as block GEMMs) against the sum of the operators built on the
+    Fock space, for several pairs of ranks 0, 1/2, 1 and particle changes."""
+    nl, nr, n, tS = 2, 2, 4, 2
+    rng = np.random.default_rng(31)
+    left, right = su2.multiplets(nl), su2.multiplets(nr)
+    lsec = [(M.n, M.tS, M.dim) for M in left]
+    rsec = [(M.n, M.tS, M.dim) for M in right]
+    full_l = DetSpace.full(nl)
+    nL = np.bitwise_count(full_l.dets.astype(np.uint64)).astype(int)
+    pairs, O = [], 0
+    for (dn, tk), c in zip([(0, 0), (1, 1), (-1, 1), (0, 2), (2, 2)], [0.7, -1.3, 0.4, 2.0, -0.5]):
+        ta, A = block_tensor(left, nl, dn, tk, rng)
+        tb, B = block_tensor(right, nr, -dn, tk, rng)
+        pb = abs(dn) % 2
+        sign = np.diag((-1.0) ** (pb * nL))
+        O = O + c * sum(su2.clebsch_gordan(tk, tq, tk, -tq, 0, 0) * np.kron(B[-tq], A[tq] @ sign)
+                        for tq in range(-tk, tk + 1, 2))
+        pairs.append((c, tk, pb, ta, tb))
+    basis = su2.coupled_basis(left, right, n, tS)
+    P, space = su2.coupled_vectors(left, right, nl, nr, n, tS, tS, basis)
+    idx = np.asarray(space.dets)
+    psi_flat = rng.normal(size=len(basis))
+    ref = P.T @ (O[np.ix_(idx, idx)] @ (P @ psi_flat))
+    blocks = su2.coupled_blocks(lsec, rsec, n, tS)
+    psi = {k: np.zeros((lsec[k[0]][2], rsec[k[1]][2])) for k in blocks}
+    for c, (ia, al, ib, be) in enumerate(basis):
+        psi[(ia, ib)][al, be] = psi_flat[c]
+    got = su2.contract_scalar_products(lsec, rsec, n, tS, psi, pairs)
+    got_flat = np.array([got[(ia, ib)][al, be] for (ia, al, ib, be) in basis])
+    assert np.abs(ref).max() > 1e-2
+    assert np.allclose(got_flat, ref, atol=1e-11)
