@@ -347,6 +347,71 @@ dmrg_status dmrg_energy(dmrg_ctx ctx, const double* h, const double* eri, const 
                         int32_t precision, double* sigma_out, double* grad_psi, double* energy_out,
                         double* norm2_out);
 
+/* ---- spin adaptation (SU(2)): the contraction of a spin-adapted sigma ----
+ *
+ * Spin-adapted DMRG counts bond states in multiplets (Numerical procedure
+ * section: fixed D_SU(2), Fig. 2-3).  The window vector of total N and spin
+ * S is stored reduced, over coupled blocks (a, b) of a left multiplet sector
+ * a = (N_a, 2S_a, d_a) and a right sector b with N_a + N_b = N and S in
+ * S_a x S_b: the blocks in order of a, then b, each d_a x d_b row-major
+ * (dmrg_su2_psi_size gives the length).  A spin-adapted sigma is a sum of
+ * scalar products c [A^k x B^k]^0 of a left and a right tensor operator of
+ * rank k (k = 0, 1/2, 1, ...), given by their reduced matrices in the
+ * Clebsch-Gordan convention of the Wigner-Eckart theorem,
+ * <a' S' M'|T^k_q|a S M> = <S M; k q|S' M'> <a' S'||T^k||a S>.  Block by
+ * block,
+ *   sigma[a', b'] += c (-1)^(p N_a) W A[a', a] psi[a, b] B[b', b]^T,
+ *   W = (-1)^(S_a + S_b' + S + k) sqrt((2S_a'+1)(2S_b'+1)/(2k+1))
+ *       {S_a S_b S; S_b' S_a' k}   (a Wigner 6j symbol),
+ * p the fermion parity of B and N_a the electrons of the ket's left part.
+ * The library runs it as two stages of its FP64 grouped GEMM (T = psi B^T,
+ * then sigma += W c A T).  Building the spin-adapted operators of a
+ * Hamiltonian (renormalisation with 9j recoupling) is not part of the
+ * library: the operators are the caller's. */
+typedef struct {
+  int32_t n_left, n_right;      /* multiplet sectors of the left / right block */
+  const int32_t* left_n;        /* host arrays of n_left entries: N, 2S, dimension */
+  const int32_t* left_two_s;
+  const int32_t* left_dim;
+  const int32_t* right_n;       /* host arrays of n_right entries */
+  const int32_t* right_two_s;
+  const int32_t* right_dim;
+  int32_t n_elec, two_s;        /* total N and 2S of the window */
+} dmrg_su2_window;
+
+typedef struct {
+  int32_t n_blocks;
+  const int32_t* out_sector;    /* host: sector of the block's rows (bra) */
+  const int32_t* in_sector;     /* host: sector of its columns (ket) */
+  const int64_t* offset;        /* host: element offset of the block in data */
+  const double* data;           /* device: blocks d_out x d_in row-major */
+} dmrg_su2_operator;
+
+typedef struct {
+  int32_t left_op, right_op;    /* indices into the operator arrays */
+  int32_t two_k;                /* rank k, doubled */
+  int32_t parity;               /* fermion parity of the right operator (0, 1) */
+  double coef;
+} dmrg_su2_pair;
+
+/* Length of the reduced window vector; host only, no context.  Errors:
+ * DMRG_ERR_INVALID_ARG for a NULL pointer, a non-positive dimension, a
+ * sector whose 2S and N differ in parity or a negative N or 2S. */
+dmrg_status dmrg_su2_psi_size(const dmrg_su2_window* window, int64_t* n);
+
+/* sigma = sum over pairs of c [A^k x B^k]^0 psi (the rule above) in FP64.
+ * psi, sigma: device pointers of dmrg_su2_psi_size elements, caller-owned;
+ * operators: host descriptors of device blocks (a block whose sectors or
+ * ranks cannot couple contributes nothing).  Errors: DMRG_ERR_INVALID_ARG for
+ * an invalid window, an operator index out of range, a block sector out of
+ * range, or a pair whose right parity is not 0 or 1.  Stream-ordered on the
+ * context stream; its workspace is released before returning (the call
+ * synchronises the stream). */
+dmrg_status dmrg_su2_sigma(dmrg_ctx ctx, const dmrg_su2_window* window, int32_t n_left_ops,
+                           const dmrg_su2_operator* left_ops, int32_t n_right_ops,
+                           const dmrg_su2_operator* right_ops, int32_t n_pairs,
+                           const dmrg_su2_pair* pairs, const double* psi, double* sigma);
+
 /* Diagnostic: copies diag(H_eff) of the current window (the Davidson
  * preconditioner; psi layout, device pointer, length dmrg_psi_size). */
 dmrg_status dmrg_debug_diag(dmrg_ctx ctx, double* out);

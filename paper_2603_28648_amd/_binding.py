@@ -81,6 +81,25 @@ class DavidsonStats(ctypes.Structure):
                 ("stage_history", ctypes.c_int32 * 256)]
 
 
+class Su2Window(ctypes.Structure):
+    _fields_ = [("n_left", ctypes.c_int32), ("n_right", ctypes.c_int32),
+                ("left_n", ctypes.POINTER(ctypes.c_int32)), ("left_two_s", ctypes.POINTER(ctypes.c_int32)),
+                ("left_dim", ctypes.POINTER(ctypes.c_int32)), ("right_n", ctypes.POINTER(ctypes.c_int32)),
+                ("right_two_s", ctypes.POINTER(ctypes.c_int32)), ("right_dim", ctypes.POINTER(ctypes.c_int32)),
+                ("n_elec", ctypes.c_int32), ("two_s", ctypes.c_int32)]
+
+
+class Su2Operator(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_int32), ("out_sector", ctypes.POINTER(ctypes.c_int32)),
+                ("in_sector", ctypes.POINTER(ctypes.c_int32)), ("offset", ctypes.POINTER(ctypes.c_int64)),
+                ("data", ctypes.c_void_p)]
+
+
+class Su2Pair(ctypes.Structure):
+    _fields_ = [("left_op", ctypes.c_int32), ("right_op", ctypes.c_int32), ("two_k", ctypes.c_int32),
+                ("parity", ctypes.c_int32), ("coef", ctypes.c_double)]
+
+
 EXPORTS = {
     "dmrg_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p]),
     "dmrg_destroy": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -114,6 +133,10 @@ EXPORTS = {
                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_int32,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]),
+    "dmrg_su2_psi_size": (ctypes.c_int32, [ctypes.POINTER(Su2Window), ctypes.POINTER(ctypes.c_int64)]),
+    "dmrg_su2_sigma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Su2Window), ctypes.c_int32,
+                                        ctypes.POINTER(Su2Operator), ctypes.c_int32, ctypes.POINTER(Su2Operator),
+                                        ctypes.c_int32, ctypes.POINTER(Su2Pair), ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -174,6 +197,29 @@ def _mps(mps_arrays, window, keep):
     keep.append(ptrs)
     return Mps(K, int(window), *[_ptr(x, ctypes.c_int32) for x in arrs],
                ctypes.cast(ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_double))))
+
+
+def _su2_window(left_sectors, right_sectors, n_elec, two_s, keep):
+    """left_sectors / right_sectors: lists of (N, 2S, dimension)."""
+    cols = []
+    for secs in (left_sectors, right_sectors):
+        a = np.asarray(secs, dtype=np.int32).reshape(-1, 3)
+        cols += [np.ascontiguousarray(a[:, i]) for i in range(3)]
+    keep += cols
+    return Su2Window(len(left_sectors), len(right_sectors), *[_ptr(c, ctypes.c_int32) for c in cols],
+                     int(n_elec), int(two_s))
+
+
+def su2_psi_size(left_sectors, right_sectors, n_elec, two_s):
+    """Length of the reduced spin-adapted window vector (dmrg_su2_psi_size; no GPU)."""
+    lib = load_library()
+    keep = []
+    w = _su2_window(left_sectors, right_sectors, n_elec, two_s, keep)
+    n = ctypes.c_int64()
+    st = lib.dmrg_su2_psi_size(ctypes.byref(w), ctypes.byref(n))
+    if st < 0:
+        raise DMRGError(st, lib.dmrg_last_error(None).decode())
+    return n.value
 
 
 def validate(h, eri, n_elec, two_sz, mps_arrays=None, window=0, e_core=0.0):
@@ -468,6 +514,32 @@ class Context:
                                          _dev_ptr(grad) if grad is not None else None,
                                          ctypes.byref(e), ctypes.byref(nrm)), self.h)
         return e.value, nrm.value
+
+    def su2_sigma(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, psi, out):
+        """dmrg_su2_sigma.  Sectors: lists of (N, 2S, dimension).  An operator is
+        (blocks, data): blocks a list of (out sector, in sector, element
+        offset), data a contiguous float64 CUDA tensor holding the row-major
+        blocks.  pairs: (left op, right op, 2k, parity of the right op, coef)."""
+        keep = []
+        w = _su2_window(left_sectors, right_sectors, n_elec, two_s, keep)
+
+        def ops(lst):
+            arr = (Su2Operator * max(1, len(lst)))()
+            for i, (blocks, data) in enumerate(lst):
+                b = np.asarray(blocks, dtype=np.int64).reshape(-1, 3)
+                o, n_, off = (np.ascontiguousarray(b[:, 0], dtype=np.int32),
+                              np.ascontiguousarray(b[:, 1], dtype=np.int32), np.ascontiguousarray(b[:, 2]))
+                keep.extend([o, n_, off, data])
+                arr[i] = Su2Operator(len(b), _ptr(o, ctypes.c_int32), _ptr(n_, ctypes.c_int32),
+                                     _ptr(off, ctypes.c_int64), _dev_ptr(data))
+            return arr
+
+        la, ra = ops(left_ops), ops(right_ops)
+        pa = (Su2Pair * max(1, len(pairs)))(*[Su2Pair(int(l), int(r), int(k), int(p), float(c))
+                                               for l, r, k, p, c in pairs])
+        self._check(self.lib.dmrg_su2_sigma(self.h, ctypes.byref(w), len(left_ops), la, len(right_ops), ra,
+                                            len(pairs), pa, _dev_ptr(psi), _dev_ptr(out)), self.h)
+        return out
 
     def debug_diag(self, out):
         self._check(self.lib.dmrg_debug_diag(self.h, _dev_ptr(out)), self.h)

@@ -19,7 +19,8 @@ OUT = os.path.join(HERE, "libdmrg_mi355x.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["kernels.hip", "kernels_bf16.hip", "kernels_pack.hip", "kernels_oz.hip", "engine.cpp",
-           "gemm_mixed.cpp", "davidson.cpp", "truncate.cpp", "backward.cpp", "noalloc.hip", "capi.cpp"]
+           "gemm_mixed.cpp", "davidson.cpp", "truncate.cpp", "backward.cpp", "noalloc.hip", "su2.cpp",
+           "capi.cpp"]
 ARCH = "gfx950"
 
 

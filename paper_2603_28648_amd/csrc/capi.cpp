@@ -13,6 +13,7 @@
 #include "backward.h"
 #include "davidson.h"
 #include "engine.h"
+#include "su2.h"
 #include "noalloc.h"
 #include "truncate.h"
 
@@ -570,6 +571,29 @@ dmrg_status dmrg_sigma_timing(dmrg_ctx c, int32_t mode, dmrg_sigma_times* out) {
       for (auto& a : p.s2) out->flops_stage2 += a.flops;
       out->flops_pinned = p.p1.flops + p.p2.flops;
     }
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_su2_psi_size(const dmrg_su2_window* window, int64_t* n) {
+  return guarded(nullptr, [&]() -> dmrg_status {
+    DMRG_REQUIRE(window && n, kErrInvalidArg, "su2_psi_size: NULL pointer");
+    *n = su2_psi_size(*window);
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_su2_sigma(dmrg_ctx c, const dmrg_su2_window* window, int32_t n_left_ops,
+                           const dmrg_su2_operator* left_ops, int32_t n_right_ops,
+                           const dmrg_su2_operator* right_ops, int32_t n_pairs, const dmrg_su2_pair* pairs,
+                           const double* psi, double* sigma) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(window, kErrInvalidArg, "su2_sigma: NULL window");
+    DMRG_REQUIRE(n_left_ops >= 0 && n_right_ops >= 0 && (n_left_ops == 0 || left_ops) &&
+                     (n_right_ops == 0 || right_ops),
+                 kErrInvalidArg, "su2_sigma: NULL operator array");
+    su2_sigma(c->stream, *window, n_left_ops, left_ops, n_right_ops, right_ops, n_pairs, pairs, psi, sigma);
     return kOk;
   });
 }

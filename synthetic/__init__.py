@@ -1,7 +1,8 @@
 """Seeded synthetic inputs shared by the CPU oracle and the GPU library tests.
 
 This package only draws random numbers and lays them out in the documented
-exchange formats (integral arrays, block-sparse MPS tensors).  It contains
+exchange formats (integral arrays, block-sparse MPS tensors, spin-adapted
+sectors and reduced operator blocks in `synthetic.su2`).  It contains
 none of the DMRG arithmetic: no operators, no Hamiltonian application, no
 renormalisation.  Both the oracle and the library consume what it produces.
 """
