@@ -1134,6 +1134,30 @@ std::unique_ptr<SigmaPlan> plan_sigma(const Problem& P, const Mps& m, const Env&
               a.flops, a.probs.size(), (long long)kmax, a.probs.empty() ? 0.0 : (double)ksum / a.probs.size());
     }
     fprintf(stderr, "[dmrg] stage-2 FLOPs with the left identity as operand: %.3e\n", plan->flops_s2_ident);
+    // MFMA work a BF16 launch issues per stage against the algorithmic
+    // FLOPs, for square tiles of side T: whole tiles, or only the 16 x 16
+    // blocks holding valid outputs; each segment's k in slabs of 32
+    for (int st = 0; st < 2; ++st)
+      for (int T : {64, 128, 256}) {
+        double alg = 0, whole = 0, blocks = 0, kexact = 0;
+        for (const AStage& a : st ? plan->s2 : plan->s1)
+          for (const AProb& pb : a.probs) {
+            double k32 = 0, k = 0;
+            for (int64_t q = pb.s0; q < pb.s1; ++q) {
+              k32 += 32.0 * ((a.segs[q].k + 31) / 32);
+              k += a.segs[q].k;
+            }
+            const double m16 = 16.0 * ((pb.m + 15) / 16), n16 = 16.0 * ((pb.n + 15) / 16);
+            const double mt = (double)T * ((pb.m + T - 1) / T), nt = (double)T * ((pb.n + T - 1) / T);
+            alg += 2.0 * pb.m * pb.n * k;
+            whole += 2.0 * mt * nt * k32;
+            blocks += 2.0 * m16 * n16 * k32;
+            kexact += 2.0 * m16 * n16 * k;
+          }
+        fprintf(stderr, "[dmrg] stage %d, %d x %d tiles: issued/algorithmic MFMA work %.2f (whole tiles), %.2f "
+                "(valid 16x16 blocks), %.2f (valid blocks, exact k)\n", st + 1, T, T, whole / alg, blocks / alg,
+                kexact / alg);
+      }
   }
   {
     std::vector<AStage> a1, a2;

@@ -201,6 +201,11 @@ __global__ __launch_bounds__(64 * waves_of(BM, BN), (TileCfg<BM, BN, ST>::MIN_BL
   // scaled at the end (multi-segment tiles have +-1 scales, checked on upload)
   double fscale = 1.0;
 
+  // A wave whose rows or columns all lie outside the tile's valid part
+  // multiplies zero rows of the slab only: it skips its fragment reads and
+  // MFMAs (and still loads its share of each slab)
+  const bool idle = __builtin_amdgcn_readfirstlane((int)(wm >= t.m || wn >= t.n)) != 0;
+
   if (t.seg_begin < t.seg_end) {
     // producer cursor: next slab to load; consumer cursor: next slab to multiply
     int ps = t.seg_begin, pk0 = 0;
@@ -250,29 +255,31 @@ __global__ __launch_bounds__(64 * waves_of(BM, BN), (TileCfg<BM, BN, ST>::MIN_BL
       const uint16_t* Blo = Bhi + BN * 32 * (NP - 1);
       // MFMAs on the slab; a -1 scale flips the sign of A
       const uint32_t nmask = cg.alpha == -1.0 ? 0x80008000u : 0u;
-      bf16x8 ah[FM], bh[FN];
+      if (!idle) {
+        bf16x8 ah[FM], bh[FN];
 #pragma unroll
-      for (int x = 0; x < FM; ++x) ah[x] = neg_if(frag(Ahi, wm + 16 * x + lr, lk), nmask);
+        for (int x = 0; x < FM; ++x) ah[x] = neg_if(frag(Ahi, wm + 16 * x + lr, lk), nmask);
 #pragma unroll
-      for (int x = 0; x < FN; ++x) bh[x] = frag(Bhi, wn + 16 * x + lr, lk);
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-          sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], sacc[a][b], 0, 0, 0);
-      if (X3) {
-        bf16x8 al[FM], bl[FN];
-#pragma unroll
-        for (int x = 0; x < FM; ++x) al[x] = neg_if(frag(Alo, wm + 16 * x + lr, lk), nmask);
-#pragma unroll
-        for (int x = 0; x < FN; ++x) bl[x] = frag(Blo, wn + 16 * x + lr, lk);
+        for (int x = 0; x < FN; ++x) bh[x] = frag(Bhi, wn + 16 * x + lr, lk);
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
-          for (int b = 0; b < FN; ++b) {
-            sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], sacc[a][b], 0, 0, 0);
-            sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], sacc[a][b], 0, 0, 0);
-          }
+          for (int b = 0; b < FN; ++b)
+            sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], sacc[a][b], 0, 0, 0);
+        if (X3) {
+          bf16x8 al[FM], bl[FN];
+#pragma unroll
+          for (int x = 0; x < FM; ++x) al[x] = neg_if(frag(Alo, wm + 16 * x + lr, lk), nmask);
+#pragma unroll
+          for (int x = 0; x < FN; ++x) bl[x] = frag(Blo, wn + 16 * x + lr, lk);
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b) {
+              sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], sacc[a][b], 0, 0, 0);
+              sacc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], sacc[a][b], 0, 0, 0);
+            }
+        }
       }
       ++done;
       ck0 += kBK;
