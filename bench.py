@@ -141,6 +141,53 @@ def cpu_baseline(m, reps=2, seed=0):
     return t_model, t_spent, len(counts) + 1, sum(counts.values()) + 2
 
 
+def su2_bench(ctx, steps):
+    """The spin-adapted FP64 sigma (dmrg_su2_plan_*) on the CAS(89,102)-shaped
+    S = 5/2 workload with 2048 multiplets a side: plan once, one untimed
+    call, then `steps` calls timed between device synchronisations."""
+    import torch
+    from synthetic.su2 import cas89_102_workload
+    t0 = time.perf_counter()
+    w = cas89_102_workload()
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = ctx.su2_plan(w["left_sectors"], w["right_sectors"], w["n"], w["two_s"], w["left_ops"],
+                        w["right_ops"], w["pairs"])
+    t_plan = time.perf_counter() - t0
+    try:
+        info = plan.info()
+        out = torch.empty_like(w["psi"])
+        plan.sigma(w["psi"], out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.sigma(w["psi"], out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+    finally:
+        plan.close()
+    flops = info["flops_stage1"] + info["flops_stage2"]
+    tflops = flops / (ms * 1e-3) / 1e12
+    leg = {"workload": "cas89_102 S=5/2: 51|51 orbitals, 2048 multiplets a side, "
+                       f"{len(w['pairs'])} operator pairs, random reduced blocks",
+           "psi_size": info["psi_size"], "pairs": len(w["pairs"]),
+           "operator_gb": (w["left_data"].numel() + w["right_data"].numel()) * 8 / 1e9,
+           "chunks": info["n_chunks"], "segments": info["n_segments"],
+           "workspace_gb": info["workspace_bytes"] / 1e9, "flops": flops,
+           "flops_stages": [info["flops_stage1"], info["flops_stage2"]],
+           "gen_s": round(t_gen, 2), "plan_s": round(t_plan, 2), "ms": ms, "tflops": tflops,
+           "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_TFLOPS["fp64"],
+                        "unit": "TFLOP/s", "frac": tflops / PEAK_TFLOPS["fp64"],
+                        "kernel": "k_gemm_f64 (stage-1 and stage-2 launches of every chunk)"}}
+    log(f"[bench] su2 sigma (CAS(89,102) S=5/2, {len(w['pairs'])} pairs, {info['n_chunks']} chunks, "
+        f"{info['n_segments']} block products): {ms:.1f} ms, {tflops:.1f} TFLOP/s FP64 "
+        f"({100 * tflops / PEAK_TFLOPS['fp64']:.1f}% of peak); plan {t_plan:.1f} s, inputs {t_gen:.1f} s")
+    del w
+    torch.cuda.empty_cache()
+    return leg
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +209,9 @@ def main():
                          "refined ladder only; 0: skip")
     ap.add_argument("--ozaki-steps", type=int, default=2,
                     help="Ozaki-scheme (FP64 emulated on INT8) sigma steps timed beside the headline (0: skip)")
+    ap.add_argument("--su2-steps", type=int, default=3,
+                    help="spin-adapted (SU(2)) FP64 sigma steps on the CAS(89,102)-shaped S = 5/2 workload "
+                         "with 2048 multiplets a side, timed beside the headline (0: skip)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch each sigma kernel by kernel instead of replaying a captured HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -381,6 +431,9 @@ def main():
             f"({ozaki['tflops']:.1f} TFLOP/s FP64-equivalent), stage1 {ozaki['stage1_ms']:.1f} + stage2 "
             f"{ozaki['stage2_ms']:.1f} + slicing {ozaki['slicing_ms']:.1f} + pinned {ozaki['pinned_fp64_ms']:.1f} ms; "
             f"INT8 {int8_tops:.0f} TOP/s; |dsigma|/|sigma| = {rel_oz:.2e}")
+    su2_leg = None
+    if args.su2_steps > 0:
+        su2_leg = su2_bench(ctx, args.su2_steps)
     cpu = None
     if not args.no_cpu_baseline:
         t_cpu, t_spent, n_cls, n_terms = cpu_baseline(m, args.cpu_reps)
@@ -440,7 +493,8 @@ def main():
                    "bf16_sigma": bf16,
                    "davidson": dav,
                    "davidson_solve": solve,
-                   "ozaki": ozaki},
+                   "ozaki": ozaki,
+                   "su2": su2_leg},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",

@@ -404,13 +404,54 @@ dmrg_status dmrg_su2_psi_size(const dmrg_su2_window* window, int64_t* n);
  * operators: host descriptors of device blocks (a block whose sectors or
  * ranks cannot couple contributes nothing).  Errors: DMRG_ERR_INVALID_ARG for
  * an invalid window, an operator index out of range, a block sector out of
- * range, or a pair whose right parity is not 0 or 1.  Stream-ordered on the
- * context stream; its workspace is released before returning (the call
- * synchronises the stream). */
+ * range, or a pair whose right parity is not 0 or 1.  One call is
+ * dmrg_su2_plan_create, dmrg_su2_plan_sigma and dmrg_su2_plan_destroy; it
+ * synchronises the context stream before returning. */
 dmrg_status dmrg_su2_sigma(dmrg_ctx ctx, const dmrg_su2_window* window, int32_t n_left_ops,
                            const dmrg_su2_operator* left_ops, int32_t n_right_ops,
                            const dmrg_su2_operator* right_ops, int32_t n_pairs,
                            const dmrg_su2_pair* pairs, const double* psi, double* sigma);
+
+/* A spin-adapted sigma planned once and applied many times (the Davidson
+ * iterations of one window).  dmrg_su2_plan_create checks its arguments as
+ * dmrg_su2_sigma does, selects the block products that some pair needs,
+ * splits the right operators into chunks whose stage-1 products fit the
+ * context's workspace budget (8 GiB, DMRG_WS_BUDGET_MB at dmrg_create), and
+ * uploads the GEMM descriptors.  The plan keeps the device addresses of the
+ * operator blocks: their memory must stay allocated and unchanged while the
+ * plan lives.  It owns device copies of psi and sigma and the workspace.
+ * A plan belongs to its context: it is used and destroyed through that
+ * context, and dmrg_destroy releases plans still alive (their handles then
+ * become invalid).  Errors: those of dmrg_su2_sigma; DMRG_ERR_OOM when
+ * device memory runs out. */
+typedef struct dmrg_su2_plan_s* dmrg_su2_plan;
+dmrg_status dmrg_su2_plan_create(dmrg_ctx ctx, const dmrg_su2_window* window, int32_t n_left_ops,
+                                 const dmrg_su2_operator* left_ops, int32_t n_right_ops,
+                                 const dmrg_su2_operator* right_ops, int32_t n_pairs,
+                                 const dmrg_su2_pair* pairs, dmrg_su2_plan* plan);
+
+/* sigma = the plan's contraction of psi (device pointers of psi_size
+ * elements, caller-owned; sigma may be psi itself).  Stream-ordered on the
+ * context stream, no synchronisation, no allocation.  Calls on one plan run
+ * in stream order; psi and sigma may be reused once the stream reaches the
+ * end of the call.  DMRG_ERR_INVALID_ARG for a plan that is not one of
+ * this context's. */
+dmrg_status dmrg_su2_plan_sigma(dmrg_ctx ctx, dmrg_su2_plan plan, const double* psi, double* sigma);
+
+typedef struct {
+  int64_t psi_size;        /* elements of psi and sigma */
+  int32_t n_chunks;        /* workspace chunks (stage-1 + stage-2 launch pairs) */
+  int32_t pad;
+  int64_t n_segments;      /* block products of both stages */
+  int64_t workspace_bytes; /* stage-1 workspace (the largest chunk) */
+  double flops_stage1;     /* 2 d_a d_b d_b' per stage-1 product */
+  double flops_stage2;     /* 2 d_a' d_a d_b' per stage-2 product */
+} dmrg_su2_info;
+dmrg_status dmrg_su2_plan_info(dmrg_ctx ctx, dmrg_su2_plan plan, dmrg_su2_info* out);
+
+/* Synchronises the context stream, then releases the plan.  A NULL plan is
+ * a no-op. */
+dmrg_status dmrg_su2_plan_destroy(dmrg_ctx ctx, dmrg_su2_plan plan);
 
 /* Diagnostic: copies diag(H_eff) of the current window (the Davidson
  * preconditioner; psi layout, device pointer, length dmrg_psi_size). */

@@ -95,6 +95,12 @@ class Su2Operator(ctypes.Structure):
                 ("data", ctypes.c_void_p)]
 
 
+class Su2Info(ctypes.Structure):
+    _fields_ = [("psi_size", ctypes.c_int64), ("n_chunks", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("n_segments", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("flops_stage1", ctypes.c_double), ("flops_stage2", ctypes.c_double)]
+
+
 class Su2Pair(ctypes.Structure):
     _fields_ = [("left_op", ctypes.c_int32), ("right_op", ctypes.c_int32), ("two_k", ctypes.c_int32),
                 ("parity", ctypes.c_int32), ("coef", ctypes.c_double)]
@@ -137,6 +143,13 @@ EXPORTS = {
     "dmrg_su2_sigma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Su2Window), ctypes.c_int32,
                                         ctypes.POINTER(Su2Operator), ctypes.c_int32, ctypes.POINTER(Su2Operator),
                                         ctypes.c_int32, ctypes.POINTER(Su2Pair), ctypes.c_void_p, ctypes.c_void_p]),
+    "dmrg_su2_plan_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Su2Window), ctypes.c_int32,
+                                              ctypes.POINTER(Su2Operator), ctypes.c_int32,
+                                              ctypes.POINTER(Su2Operator), ctypes.c_int32, ctypes.POINTER(Su2Pair),
+                                              ctypes.POINTER(ctypes.c_void_p)]),
+    "dmrg_su2_plan_sigma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "dmrg_su2_plan_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Su2Info)]),
+    "dmrg_su2_plan_destroy": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -220,6 +233,41 @@ def su2_psi_size(left_sectors, right_sectors, n_elec, two_s):
     if st < 0:
         raise DMRGError(st, lib.dmrg_last_error(None).decode())
     return n.value
+
+
+class Su2Plan:
+    """A spin-adapted sigma planned once (dmrg_su2_plan_*).  sigma(psi, out)
+    is stream-ordered on the context stream; close() (or leaving a with
+    block) synchronises and releases the plan."""
+
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    def sigma(self, psi, out):
+        n = self.info()["psi_size"]
+        if psi.numel() != n or out.numel() != n:
+            raise ValueError(f"expected {n} elements, got {psi.numel()} and {out.numel()}")
+        self.ctx._check(self.ctx.lib.dmrg_su2_plan_sigma(self.ctx.h, self.h, _dev_ptr(psi), _dev_ptr(out)),
+                        self.ctx.h)
+        return out
+
+    def info(self):
+        o = Su2Info()
+        self.ctx._check(self.ctx.lib.dmrg_su2_plan_info(self.ctx.h, self.h, ctypes.byref(o)), self.ctx.h)
+        return {"psi_size": o.psi_size, "n_chunks": o.n_chunks, "n_segments": o.n_segments,
+                "workspace_bytes": o.workspace_bytes, "flops_stage1": o.flops_stage1,
+                "flops_stage2": o.flops_stage2}
+
+    def close(self):
+        if self.h and getattr(self.ctx, "h", None):
+            self.ctx._check(self.ctx.lib.dmrg_su2_plan_destroy(self.ctx.h, self.h), self.ctx.h)
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def validate(h, eri, n_elec, two_sz, mps_arrays=None, window=0, e_core=0.0):
@@ -515,31 +563,66 @@ class Context:
                                          ctypes.byref(e), ctypes.byref(nrm)), self.h)
         return e.value, nrm.value
 
-    def su2_sigma(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, psi, out):
-        """dmrg_su2_sigma.  Sectors: lists of (N, 2S, dimension).  An operator is
-        (blocks, data): blocks a list of (out sector, in sector, element
-        offset), data a contiguous float64 CUDA tensor holding the row-major
-        blocks.  pairs: (left op, right op, 2k, parity of the right op, coef)."""
-        keep = []
+    def _su2_args(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, keep):
+        """ctypes arguments of the spin-adapted calls.  Sectors: lists of
+        (N, 2S, dimension).  An operator is (blocks, data) or (blocks, data,
+        base): blocks a list of (out sector, in sector, element offset), data
+        a contiguous float64 CUDA tensor holding the row-major blocks from
+        element base on (default 0).  pairs: (left op, right op, 2k, parity of
+        the right op, coef)."""
         w = _su2_window(left_sectors, right_sectors, n_elec, two_s, keep)
 
-        def ops(lst):
+        def ops(lst, sectors):
+            dims = np.asarray([d for _, _, d in sectors], dtype=np.int64)
             arr = (Su2Operator * max(1, len(lst)))()
-            for i, (blocks, data) in enumerate(lst):
+            for i, op in enumerate(lst):
+                blocks, data = op[0], op[1]
+                base = int(op[2]) if len(op) > 2 else 0
                 b = np.asarray(blocks, dtype=np.int64).reshape(-1, 3)
                 o, n_, off = (np.ascontiguousarray(b[:, 0], dtype=np.int32),
                               np.ascontiguousarray(b[:, 1], dtype=np.int32), np.ascontiguousarray(b[:, 2]))
+                ptr = _dev_ptr(data).value
+                if len(b):
+                    # every block inside the tensor (the library only sees pointers)
+                    if o.min() < 0 or n_.min() < 0 or o.max() >= len(dims) or n_.max() >= len(dims):
+                        raise ValueError(f"operator {i}: block sector out of range")
+                    end = base + int((off + dims[o] * dims[n_]).max())
+                    if base < 0 or off.min() < 0 or end > data.numel():
+                        raise ValueError(f"operator {i}: blocks reach past its data tensor")
                 keep.extend([o, n_, off, data])
                 arr[i] = Su2Operator(len(b), _ptr(o, ctypes.c_int32), _ptr(n_, ctypes.c_int32),
-                                     _ptr(off, ctypes.c_int64), _dev_ptr(data))
+                                     _ptr(off, ctypes.c_int64), ptr + 8 * base)
             return arr
 
-        la, ra = ops(left_ops), ops(right_ops)
+        la, ra = ops(left_ops, left_sectors), ops(right_ops, right_sectors)
         pa = (Su2Pair * max(1, len(pairs)))(*[Su2Pair(int(l), int(r), int(k), int(p), float(c))
                                                for l, r, k, p, c in pairs])
-        self._check(self.lib.dmrg_su2_sigma(self.h, ctypes.byref(w), len(left_ops), la, len(right_ops), ra,
-                                            len(pairs), pa, _dev_ptr(psi), _dev_ptr(out)), self.h)
+        keep.extend([la, ra, pa])
+        return ctypes.byref(w), len(left_ops), la, len(right_ops), ra, len(pairs), pa
+
+    def su2_sigma(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, psi, out):
+        """dmrg_su2_sigma (arguments as in _su2_args); synchronises."""
+        keep = []
+        args = self._su2_args(left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, keep)
+        self._su2_check_vectors(left_sectors, right_sectors, n_elec, two_s, psi, out)
+        self._check(self.lib.dmrg_su2_sigma(self.h, *args, _dev_ptr(psi), _dev_ptr(out)), self.h)
         return out
+
+    @staticmethod
+    def _su2_check_vectors(left_sectors, right_sectors, n_elec, two_s, *vecs):
+        n = su2_psi_size(left_sectors, right_sectors, n_elec, two_s)
+        for v in vecs:
+            if v.numel() != n:
+                raise ValueError(f"expected {n} elements, got {v.numel()}")
+
+    def su2_plan(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs):
+        """dmrg_su2_plan_create: a Su2Plan (arguments as in _su2_args).  The
+        operator tensors must outlive the plan."""
+        keep = []
+        args = self._su2_args(left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, keep)
+        h = ctypes.c_void_p()
+        self._check(self.lib.dmrg_su2_plan_create(self.h, *args, ctypes.byref(h)), self.h)
+        return Su2Plan(self, h)
 
     def debug_diag(self, out):
         self._check(self.lib.dmrg_debug_diag(self.h, _dev_ptr(out)), self.h)

@@ -34,7 +34,11 @@ struct dmrg_ctx_s {
   bool use_graphs = false;               // sigma replayed from HIP graphs
   DevBuf next_psi;                       // guess for the window left by dmrg_truncate
   int64_t next_size = -1;
+  std::map<dmrg_su2_plan, std::unique_ptr<Su2Plan>> su2_plans;  // live spin-adapted plans
 };
+
+// A plan handle is an identity token; the context owns the plan it names.
+struct dmrg_su2_plan_s {};
 
 // Blocks kept while growing along the chain (for sweeps); larger ones are
 // rebuilt on demand.
@@ -105,6 +109,7 @@ dmrg_status dmrg_destroy(dmrg_ctx c) {
   if (!c) return kOk;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->su2_plans) delete kv.first;
   delete c;
   return kOk;
 }
@@ -590,10 +595,69 @@ dmrg_status dmrg_su2_sigma(dmrg_ctx c, const dmrg_su2_window* window, int32_t n_
   if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
   return guarded(c, [&]() -> dmrg_status {
     DMRG_REQUIRE(window, kErrInvalidArg, "su2_sigma: NULL window");
-    DMRG_REQUIRE(n_left_ops >= 0 && n_right_ops >= 0 && (n_left_ops == 0 || left_ops) &&
-                     (n_right_ops == 0 || right_ops),
-                 kErrInvalidArg, "su2_sigma: NULL operator array");
-    su2_sigma(c->stream, *window, n_left_ops, left_ops, n_right_ops, right_ops, n_pairs, pairs, psi, sigma);
+    auto plan = su2_plan(*window, n_left_ops, left_ops, n_right_ops, right_ops, n_pairs, pairs, c->ws_budget,
+                         c->stream);
+    su2_run(*plan, psi, sigma, c->stream);
+    DMRG_HIP(hipStreamSynchronize(c->stream));  // the plan's buffers are released on return
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_su2_plan_create(dmrg_ctx c, const dmrg_su2_window* window, int32_t n_left_ops,
+                                 const dmrg_su2_operator* left_ops, int32_t n_right_ops,
+                                 const dmrg_su2_operator* right_ops, int32_t n_pairs,
+                                 const dmrg_su2_pair* pairs, dmrg_su2_plan* out) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(window && out, kErrInvalidArg, "su2_plan_create: NULL pointer");
+    *out = nullptr;
+    auto plan = su2_plan(*window, n_left_ops, left_ops, n_right_ops, right_ops, n_pairs, pairs, c->ws_budget,
+                         c->stream);
+    dmrg_su2_plan h = new dmrg_su2_plan_s;
+    c->su2_plans[h] = std::move(plan);
+    *out = h;
+    return kOk;
+  });
+}
+
+static Su2Plan& su2_of(dmrg_ctx c, dmrg_su2_plan h) {
+  auto it = c->su2_plans.find(h);
+  DMRG_REQUIRE(h && it != c->su2_plans.end(), kErrInvalidArg, "su2: not a plan of this context");
+  return *it->second;
+}
+
+dmrg_status dmrg_su2_plan_sigma(dmrg_ctx c, dmrg_su2_plan h, const double* psi, double* sigma) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    su2_run(su2_of(c, h), psi, sigma, c->stream);
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_su2_plan_info(dmrg_ctx c, dmrg_su2_plan h, dmrg_su2_info* out) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(out, kErrInvalidArg, "su2_plan_info: NULL output");
+    const Su2Plan& p = su2_of(c, h);
+    *out = dmrg_su2_info{};
+    out->psi_size = p.psi_size;
+    out->n_chunks = (int32_t)p.s1.size();
+    out->n_segments = p.n_segments;
+    out->workspace_bytes = p.ws_doubles * (int64_t)sizeof(double);
+    out->flops_stage1 = p.flops1;
+    out->flops_stage2 = p.flops2;
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_su2_plan_destroy(dmrg_ctx c, dmrg_su2_plan h) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  if (!h) return kOk;
+  return guarded(c, [&]() -> dmrg_status {
+    su2_of(c, h);
+    DMRG_HIP(hipStreamSynchronize(c->stream));
+    c->su2_plans.erase(h);
+    delete h;
     return kOk;
   });
 }

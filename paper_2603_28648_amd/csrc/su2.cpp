@@ -12,11 +12,15 @@
 // of the U(1) sigma: stage 1 forms T = psi[a, b] B[b', b]^T once per right
 // operator block and left sector (NT products), stage 2 accumulates
 // W c (-1)^(p N_a) A[a', a] T into each output block (NN products), every
-// output block one problem of the grouped GEMM with its segments.
+// output block one problem of the grouped GEMM with its segments.  A plan
+// keeps both stages' descriptors per chunk of right operators, whose stage-1
+// products fit the workspace budget; stage 1 only forms the products some
+// pair's stage 2 reads.
 #include "su2.h"
 
 #include <cmath>
 #include <map>
+#include <memory>
 #include <tuple>
 #include <vector>
 
@@ -51,8 +55,9 @@ double recoupling(int tSa2, int tSb2, int tSa, int tSb, int tS, int tk) {
 struct Window {
   std::vector<int> ln, ls, ld, rn, rs, rd;
   int n, ts;
-  std::map<std::pair<int, int>, int64_t> off;  // coupled block (a, b) -> element offset
+  std::vector<int64_t> off;  // coupled block (a, b) -> element offset at a * n_right + b, or -1
   int64_t size = 0;
+  int64_t at(int a, int b) const { return off[(size_t)a * rn.size() + b]; }
 };
 
 Window parse(const dmrg_su2_window& w) {
@@ -76,13 +81,21 @@ Window parse(const dmrg_su2_window& w) {
   };
   side(w.n_left, w.left_n, w.left_two_s, w.left_dim, W.ln, W.ls, W.ld);
   side(w.n_right, w.right_n, w.right_two_s, w.right_dim, W.rn, W.rs, W.rd);
+  W.off.assign((size_t)w.n_left * w.n_right, -1);
   for (int a = 0; a < w.n_left; ++a)
     for (int b = 0; b < w.n_right; ++b)
       if (W.ln[a] + W.rn[b] == W.n && triangle(W.ls[a], W.rs[b], W.ts)) {
-        W.off[{a, b}] = W.size;
+        W.off[(size_t)a * w.n_right + b] = W.size;
         W.size += (int64_t)W.ld[a] * W.rd[b];
       }
   return W;
+}
+
+// Blocks of an operator grouped by their ket (in) sector.
+std::vector<std::vector<int>> by_in_sector(const dmrg_su2_operator& o, int ns) {
+  std::vector<std::vector<int>> v(ns);
+  for (int i = 0; i < o.n_blocks; ++i) v[o.in_sector[i]].push_back(i);
+  return v;
 }
 
 }  // namespace
@@ -106,11 +119,14 @@ double wigner_6j(int tj1, int tj2, int tj3, int tj4, int tj5, int tj6) {
 
 int64_t su2_psi_size(const dmrg_su2_window& w) { return parse(w).size; }
 
-void su2_sigma(hipStream_t s, const dmrg_su2_window& w, int n_left_ops, const dmrg_su2_operator* left_ops,
-               int n_right_ops, const dmrg_su2_operator* right_ops, int n_pairs, const dmrg_su2_pair* pairs,
-               const double* psi, double* sigma) {
+std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, const dmrg_su2_operator* left_ops,
+                                  int n_right_ops, const dmrg_su2_operator* right_ops, int n_pairs,
+                                  const dmrg_su2_pair* pairs, int64_t ws_budget, hipStream_t s) {
   const Window W = parse(w);
-  DMRG_REQUIRE(psi && sigma, kErrInvalidArg, "su2: NULL psi or sigma");
+  const int nl = (int)W.ln.size(), nr = (int)W.rn.size();
+  DMRG_REQUIRE(n_left_ops >= 0 && n_right_ops >= 0 && (n_left_ops == 0 || left_ops) &&
+                   (n_right_ops == 0 || right_ops),
+               kErrInvalidArg, "su2: NULL operator array");
   DMRG_REQUIRE(n_pairs >= 0 && (n_pairs == 0 || pairs), kErrInvalidArg, "su2: NULL pair array");
   auto check_op = [&](const dmrg_su2_operator& o, int ns) {
     DMRG_REQUIRE(o.n_blocks >= 0 && (o.n_blocks == 0 || (o.out_sector && o.in_sector && o.offset && o.data)),
@@ -120,8 +136,8 @@ void su2_sigma(hipStream_t s, const dmrg_su2_window& w, int n_left_ops, const dm
                        o.offset[i] >= 0,
                    kErrInvalidArg, "su2: operator block sector out of range");
   };
-  for (int i = 0; i < n_left_ops; ++i) check_op(left_ops[i], (int)W.ln.size());
-  for (int i = 0; i < n_right_ops; ++i) check_op(right_ops[i], (int)W.rn.size());
+  for (int i = 0; i < n_left_ops; ++i) check_op(left_ops[i], nl);
+  for (int i = 0; i < n_right_ops; ++i) check_op(right_ops[i], nr);
   for (int p = 0; p < n_pairs; ++p) {
     const dmrg_su2_pair& q = pairs[p];
     DMRG_REQUIRE(q.left_op >= 0 && q.left_op < n_left_ops && q.right_op >= 0 && q.right_op < n_right_ops,
@@ -129,74 +145,132 @@ void su2_sigma(hipStream_t s, const dmrg_su2_window& w, int n_left_ops, const dm
     DMRG_REQUIRE(q.two_k >= 0 && (q.parity == 0 || q.parity == 1), kErrInvalidArg,
                  "su2: pair rank must be >= 0 and parity 0 or 1");
   }
-  launch_fill(sigma, 0.0, W.size, s);
-  if (W.size == 0 || n_pairs == 0) {
-    DMRG_HIP(hipStreamSynchronize(s));
-    return;
-  }
-  // stage 1: T[r, block i of B_r, a] = psi[a, b] B_r[b', b]^T (d_a x d_b'), for
-  // every right operator used by a pair, every block and left sector a whose
-  // (a, b) and some (a', b') are coupled blocks
-  std::vector<char> used_r(n_right_ops, 0);
-  for (int p = 0; p < n_pairs; ++p) used_r[pairs[p].right_op] = 1;
-  std::map<std::tuple<int, int, int>, int64_t> toff;  // (r, block, a) -> workspace offset
-  int64_t wsize = 0;
-  const int nl = (int)W.ln.size();
-  for (int r = 0; r < n_right_ops; ++r) {
-    if (!used_r[r]) continue;
-    const dmrg_su2_operator& B = right_ops[r];
-    for (int i = 0; i < B.n_blocks; ++i) {
-      const int b2 = B.out_sector[i], b = B.in_sector[i];
-      for (int a = 0; a < nl; ++a) {
-        if (!W.off.count({a, b})) continue;
-        toff[{r, i, a}] = wsize;
-        wsize += (int64_t)W.ld[a] * W.rd[b2];
-      }
-    }
-  }
-  DevBuf ws((size_t)std::max<int64_t>(wsize, 1) * sizeof(double));
-  double* T = ws.as<double>();
-  {
-    GemmBatch b1;
-    for (auto& kv : toff) {
-      const int r = std::get<0>(kv.first), i = std::get<1>(kv.first), a = std::get<2>(kv.first);
-      const dmrg_su2_operator& B = right_ops[r];
-      const int b2 = B.out_sector[i], b = B.in_sector[i];
-      const size_t s0 = b1.segs.size();
-      b1.segs.push_back({psi + W.off.at({a, b}), B.data + B.offset[i], W.rd[b], W.rd[b], W.rd[b], kTransB, 1.0});
-      b1.add_problem(T + kv.second, W.rd[b2], W.ld[a], W.rd[b2], s0, s0 + 1, 0);
-    }
-    launch_gemm_f64(b1, s);
-  }
-  // stage 2: per output block (a', b'), the segments W c (-1)^(p N_a) A[a', a] T
-  std::map<std::pair<int, int>, std::vector<GemmSeg>> outs;
+  auto plan = std::make_unique<Su2Plan>();
+  plan->psi_size = W.size;
+  plan->psi.alloc((size_t)std::max<int64_t>(W.size, 1) * sizeof(double));
+  plan->sig.alloc((size_t)std::max<int64_t>(W.size, 1) * sizeof(double));
+
+  // The stage-2 products: for each pair, each ket block (a, b) of psi, each
+  // block A[a', a] of its left operator and B[b', b] of its right operator
+  // with (a', b') a coupled block and a non-zero recoupling factor.
+  struct Prod {
+    int p, i, j;  // pair, block of B, block of A
+    double scale;
+  };
+  std::vector<std::vector<Prod>> prods_of_r(n_right_ops);  // grouped by right operator
+  std::map<std::tuple<int, int, int, int, int>, double> wcache;
+  std::vector<std::vector<std::vector<int>>> lin(n_left_ops), rin(n_right_ops);
   for (int p = 0; p < n_pairs; ++p) {
     const dmrg_su2_pair& q = pairs[p];
+    if (lin[q.left_op].empty()) lin[q.left_op] = by_in_sector(left_ops[q.left_op], nl);
+    if (rin[q.right_op].empty()) rin[q.right_op] = by_in_sector(right_ops[q.right_op], nr);
     const dmrg_su2_operator& A = left_ops[q.left_op];
     const dmrg_su2_operator& B = right_ops[q.right_op];
-    for (int i = 0; i < B.n_blocks; ++i) {
-      const int b2 = B.out_sector[i], b = B.in_sector[i];
-      for (int j = 0; j < A.n_blocks; ++j) {
-        const int a2 = A.out_sector[j], a = A.in_sector[j];
-        if (!W.off.count({a, b}) || !W.off.count({a2, b2})) continue;
-        const double wc = recoupling(W.ls[a2], W.rs[b2], W.ls[a], W.rs[b], W.ts, q.two_k);
-        if (wc == 0.0) continue;
-        const double sign = (q.parity && (W.ln[a] & 1)) ? -1.0 : 1.0;
-        const int64_t to = toff.at({q.right_op, i, a});
-        outs[{a2, b2}].push_back(
-            {A.data + A.offset[j], T + to, W.ld[a], W.rd[b2], W.ld[a], 0, q.coef * sign * wc});
+    for (int a = 0; a < nl; ++a)
+      for (int b = 0; b < nr; ++b) {
+        if (W.at(a, b) < 0) continue;
+        for (int j : lin[q.left_op][a])
+          for (int i : rin[q.right_op][b]) {
+            const int a2 = A.out_sector[j], b2 = B.out_sector[i];
+            if (W.at(a2, b2) < 0) continue;
+            const auto key = std::make_tuple(W.ls[a2], W.rs[b2], W.ls[a], W.rs[b], q.two_k);
+            auto it = wcache.find(key);
+            if (it == wcache.end())
+              it = wcache.emplace(key, recoupling(W.ls[a2], W.rs[b2], W.ls[a], W.rs[b], W.ts, q.two_k)).first;
+            if (it->second == 0.0) continue;
+            const double sign = (q.parity && (W.ln[a] & 1)) ? -1.0 : 1.0;
+            prods_of_r[q.right_op].push_back({p, i, j, q.coef * sign * it->second});
+          }
+      }
+  }
+  // Stage-1 products needed per right operator: (block i of B, left sector a)
+  // -> workspace rows; chunks of right operators within the budget.
+  std::vector<std::map<std::pair<int, int>, int64_t>> need(n_right_ops);
+  std::vector<int64_t> rsize(n_right_ops, 0);
+  for (int r = 0; r < n_right_ops; ++r)
+    for (const Prod& x : prods_of_r[r]) {
+      const int a = left_ops[pairs[x.p].left_op].in_sector[x.j];
+      const int b2 = right_ops[r].out_sector[x.i];
+      if (need[r].emplace(std::make_pair(x.i, a), 0).second) rsize[r] += (int64_t)W.ld[a] * W.rd[b2];
+    }
+  std::vector<std::pair<int, int>> chunks;
+  {
+    int r0 = 0;
+    int64_t acc = 0;
+    for (int r = 0; r < n_right_ops; ++r) {
+      if (rsize[r] == 0) continue;
+      if (acc > 0 && acc + rsize[r] > ws_budget) {
+        chunks.push_back({r0, r});
+        r0 = r;
+        acc = 0;
+      }
+      acc += rsize[r];
+      plan->ws_doubles = std::max(plan->ws_doubles, acc);
+    }
+    if (acc > 0) chunks.push_back({r0, n_right_ops});
+  }
+  plan->ws.alloc((size_t)std::max<int64_t>(plan->ws_doubles, 1) * sizeof(double));
+  double* T = plan->ws.as<double>();
+  const double* P = plan->psi.as<double>();
+  double* S = plan->sig.as<double>();
+  for (auto& ch : chunks) {
+    // stage 1: T(r, i, a) = psi[a, b] B_r[b', b]^T (d_a x d_b')
+    GemmBatch b1;
+    int64_t off = 0;
+    for (int r = ch.first; r < ch.second; ++r) {
+      const dmrg_su2_operator& B = right_ops[r];
+      for (auto& kv : need[r]) {
+        const int i = kv.first.first, a = kv.first.second;
+        const int b2 = B.out_sector[i], b = B.in_sector[i];
+        kv.second = off;
+        const size_t s0 = b1.segs.size();
+        b1.segs.push_back({P + W.at(a, b), B.data + B.offset[i], W.rd[b], W.rd[b], W.rd[b], kTransB, 1.0});
+        b1.add_problem(T + off, W.rd[b2], W.ld[a], W.rd[b2], s0, s0 + 1, 0);
+        plan->flops1 += 2.0 * W.ld[a] * W.rd[b] * W.rd[b2];
+        off += (int64_t)W.ld[a] * W.rd[b2];
       }
     }
+    // stage 2: per output block (a', b'), the products W c (-1)^(p N_a) A[a', a] T
+    std::map<std::pair<int, int>, std::vector<GemmSeg>> outs;
+    for (int r = ch.first; r < ch.second; ++r)
+      for (const Prod& x : prods_of_r[r]) {
+        const dmrg_su2_operator& A = left_ops[pairs[x.p].left_op];
+        const dmrg_su2_operator& B = right_ops[r];
+        const int a2 = A.out_sector[x.j], a = A.in_sector[x.j], b2 = B.out_sector[x.i];
+        const int64_t to = need[r].at({x.i, a});
+        outs[{a2, b2}].push_back({A.data + A.offset[x.j], T + to, W.ld[a], W.rd[b2], W.ld[a], 0, x.scale});
+        plan->flops2 += 2.0 * W.ld[a2] * W.ld[a] * W.rd[b2];
+      }
+    GemmBatch b2;
+    for (auto& kv : outs) {
+      const int a2 = kv.first.first, bb2 = kv.first.second;
+      const size_t s0 = b2.segs.size();
+      for (const GemmSeg& g : kv.second) b2.segs.push_back(g);
+      b2.add_problem(S + W.at(a2, bb2), W.rd[bb2], W.ld[a2], W.rd[bb2], s0, b2.segs.size(), 1);
+    }
+    plan->n_segments += (int64_t)(b1.segs.size() + b2.segs.size());
+    plan->s1.emplace_back();
+    upload_gemm(b1, plan->s1.back());
+    plan->s2.emplace_back();
+    upload_gemm(b2, plan->s2.back());
   }
-  GemmBatch b2;
-  for (auto& kv : outs) {
-    const int a2 = kv.first.first, bb2 = kv.first.second;
-    const size_t s0 = b2.segs.size();
-    for (const GemmSeg& g : kv.second) b2.segs.push_back(g);
-    b2.add_problem(sigma + W.off.at({a2, bb2}), W.rd[bb2], W.ld[a2], W.rd[bb2], s0, b2.segs.size(), 1);
+  (void)s;
+  return plan;
+}
+
+void su2_run(Su2Plan& p, const double* psi, double* sigma, hipStream_t s) {
+  DMRG_REQUIRE(psi && sigma, kErrInvalidArg, "su2: NULL psi or sigma");
+  if (p.psi_size == 0) return;
+  // psi is copied into the plan first, so sigma may be the same buffer
+  double* P = p.psi.as<double>();
+  double* S = p.sig.as<double>();
+  DMRG_HIP(hipMemcpyAsync(P, psi, (size_t)p.psi_size * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_fill(S, 0.0, p.psi_size, s);
+  for (size_t c = 0; c < p.s1.size(); ++c) {
+    launch_gemm_f64(p.s1[c], s);
+    launch_gemm_f64(p.s2[c], s);
   }
-  launch_gemm_f64(b2, s);
-  DMRG_HIP(hipStreamSynchronize(s));  // the workspace is released on return
+  DMRG_HIP(hipMemcpyAsync(sigma, S, (size_t)p.psi_size * sizeof(double), hipMemcpyDeviceToDevice, s));
 }
 
 }  // namespace dmrg

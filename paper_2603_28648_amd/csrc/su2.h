@@ -2,10 +2,14 @@
 // the reduced window vector (see dmrg_su2_sigma in include/dmrg.h).
 #pragma once
 #include <cstdint>
+#include <memory>
+#include <vector>
 
 #include <hip/hip_runtime.h>
 
+#include "common.h"
 #include "dmrg.h"
+#include "gemm.h"
 
 namespace dmrg {
 
@@ -13,11 +17,24 @@ namespace dmrg {
 // invalid window.
 int64_t su2_psi_size(const dmrg_su2_window& w);
 
-// sigma = sum over pairs of c [A^k x B^k]^0 psi on the stream (synchronised
-// before returning: the stage-1 workspace is freed).
-void su2_sigma(hipStream_t s, const dmrg_su2_window& w, int n_left_ops, const dmrg_su2_operator* left_ops,
-               int n_right_ops, const dmrg_su2_operator* right_ops, int n_pairs, const dmrg_su2_pair* pairs,
-               const double* psi, double* sigma);
+// Device descriptors of one window's spin-adapted sigma: per workspace
+// chunk a stage-1 launch (T = psi B^T for the chunk's right operators) and a
+// stage-2 launch (sigma += W c A T), on plan-owned psi, sigma and workspace.
+struct Su2Plan {
+  int64_t psi_size = 0;
+  DevBuf psi, sig, ws;
+  std::vector<DevGemm> s1, s2;
+  int64_t n_segments = 0, ws_doubles = 0;
+  double flops1 = 0, flops2 = 0;
+};
+
+// Builds the plan (host checks as dmrg_su2_sigma; ws_budget in doubles).
+std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, const dmrg_su2_operator* left_ops,
+                                  int n_right_ops, const dmrg_su2_operator* right_ops, int n_pairs,
+                                  const dmrg_su2_pair* pairs, int64_t ws_budget, hipStream_t s);
+
+// sigma = the plan's contraction of psi, stream-ordered (no synchronisation).
+void su2_run(Su2Plan& p, const double* psi, double* sigma, hipStream_t s);
 
 // {j1 j2 j3; j4 j5 j6} for doubled arguments (Racah's formula); exposed for
 // the recoupling factors.

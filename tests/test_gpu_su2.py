@@ -12,26 +12,32 @@ import numpy as np
 import pytest
 
 from oracle import su2
-from synthetic.su2 import sector_window, random_operator, pack, unpack
+from synthetic.su2 import sector_window, random_operator, pack, unpack, cas89_102_workload
 
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
+INVALID_ARG = -1  # DMRG_ERR_INVALID_ARG
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def device_ops(lst):
+    out = []
+    for o in lst:
+        blocks, data = pack_blocks(o)
+        out.append((blocks, dev(data)))
+    return out
 
 
 def run(ctx, lsec, rsec, n, tS, lops, rops, pairs, psi_flat):
     import torch
-    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
-    def ops(lst):
-        out = []
-        for o in lst:
-            blocks, data = pack_blocks(o)
-            out.append((blocks, dev(data)))
-        return out
-    left, right = ops(lops), ops(rops)
     psi = dev(psi_flat)
     out = torch.full_like(psi, float("nan"))
-    ctx.su2_sigma(lsec, rsec, n, tS, left, right, [(l, r, tk, pb, c) for l, r, tk, pb, c in pairs], psi, out)
+    ctx.su2_sigma(lsec, rsec, n, tS, device_ops(lops), device_ops(rops), pairs, psi, out)
     torch.cuda.synchronize()
     return out.cpu().numpy()
 
@@ -62,9 +68,7 @@ CASES = [  # n, 2S, largest sector dimension, seed
 ]
 
 
-@pytest.mark.parametrize("n,tS,dmax,seed", CASES)
-def test_su2_sigma_matches_the_oracle(ctx, n, tS, dmax, seed):
-    print(f"su2 sigma: n={n} 2S={tS} dmax={dmax} seed={seed}", flush=True)
+def case_ops(n, tS, dmax, seed):
     rng = np.random.default_rng(seed)
     lsec, rsec = sector_window(n, tS, dmax, rng)
     lops, rops, pairs = [], [], []
@@ -74,36 +78,148 @@ def test_su2_sigma_matches_the_oracle(ctx, n, tS, dmax, seed):
             lops.append(random_operator(lsec, dn, tk, rng))
             pairs.append((len(lops) - 1, len(rops) - 1, tk, abs(dn) % 2, float(rng.normal())))
     size = sum(lsec[a][2] * rsec[b][2] for a, b in su2.coupled_blocks(lsec, rsec, n, tS))
+    return lsec, rsec, lops, rops, pairs, size, rng
+
+
+def close(got, ref):
+    return np.abs(got - ref).max() <= TOL * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,tS,dmax,seed", CASES)
+def test_su2_sigma_matches_the_oracle(ctx, n, tS, dmax, seed):
+    print(f"su2 sigma: n={n} 2S={tS} dmax={dmax} seed={seed}", flush=True)
+    lsec, rsec, lops, rops, pairs, size, rng = case_ops(n, tS, dmax, seed)
     psi = rng.normal(size=size)
     ref = oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs, psi)
     got = run(ctx, lsec, rsec, n, tS, lops, rops, pairs, psi)
     assert size > 1000 and np.abs(ref).max() > 1e-3
-    assert np.abs(got - ref).max() <= TOL * np.abs(ref).max()
+    assert close(got, ref)
 
 
-def test_su2_sigma_without_pairs_is_zero(ctx):
-    rng = np.random.default_rng(7)
-    lsec, rsec = sector_window(6, 0, 20, rng)
-    size = sum(lsec[a][2] * rsec[b][2] for a, b in su2.coupled_blocks(lsec, rsec, 6, 0))
-    got = run(ctx, lsec, rsec, 6, 0, [], [], [], rng.normal(size=size))
-    assert np.all(got == 0.0)
+def test_su2_plan_applied_twice_and_in_place(ctx):
+    """One plan, two window vectors, then sigma written over psi itself."""
+    import torch
+    n, tS = 10, 2
+    lsec, rsec, lops, rops, pairs, size, rng = case_ops(n, tS, 300, 3)
+    L, R = device_ops(lops), device_ops(rops)
+    with ctx.su2_plan(lsec, rsec, n, tS, L, R, pairs) as plan:
+        info = plan.info()
+        assert info["psi_size"] == size and info["n_chunks"] == 1 and info["flops_stage2"] > 0
+        for seed in (1, 2):
+            x = np.random.default_rng(seed).normal(size=size)
+            out = torch.full((size,), float("nan"), dtype=torch.float64, device="cuda")
+            plan.sigma(dev(x), out)
+            torch.cuda.synchronize()
+            assert close(out.cpu().numpy(), oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs, x))
+        buf = dev(x)
+        plan.sigma(buf, buf)
+        torch.cuda.synchronize()
+        assert close(buf.cpu().numpy(), oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs, x))
 
 
-def test_su2_sigma_rank_that_couples_nothing(ctx):
-    """A pair whose operators have no block (a particle change no sector
-    pair reaches) contributes nothing: only the other pair is seen."""
-    rng = np.random.default_rng(8)
+def test_su2_plan_in_workspace_chunks():
+    """A context with a 1 MiB stage-1 budget splits the right operators
+    into several chunks; the result is the oracle's."""
+    import os
+    import torch
+    from paper_2603_28648_amd import Context
+    old = os.environ.get("DMRG_WS_BUDGET_MB")
+    os.environ["DMRG_WS_BUDGET_MB"] = "1"
+    try:
+        c = Context(0)
+    finally:
+        if old is None:
+            del os.environ["DMRG_WS_BUDGET_MB"]
+        else:
+            os.environ["DMRG_WS_BUDGET_MB"] = old
+    try:
+        n, tS = 12, 0
+        lsec, rsec, lops, rops, pairs, size, rng = case_ops(n, tS, 260, 4)
+        psi = rng.normal(size=size)
+        L, R = device_ops(lops), device_ops(rops)
+        with c.su2_plan(lsec, rsec, n, tS, L, R, pairs) as plan:
+            info = plan.info()
+            print(f"su2 chunks: {info}", flush=True)
+            # a chunk holds at least one right operator, so one whose products
+            # exceed the budget gets a chunk of its own
+            assert info["n_chunks"] > 1
+            out = torch.empty(size, dtype=torch.float64, device="cuda")
+            plan.sigma(dev(psi), out)
+            torch.cuda.synchronize()
+        assert close(out.cpu().numpy(), oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs, psi))
+    finally:
+        c.close()
+
+
+def test_su2_plan_of_another_context_is_an_error(ctx):
+    """A plan is only valid with the context that made it, and not after
+    it was destroyed (host-side checks, no kernel runs)."""
+    import torch
+    from paper_2603_28648_amd import Context
     n, tS = 8, 0
-    lsec, rsec = sector_window(n, tS, 30, rng)
-    a = random_operator(lsec, 0, 0, rng)
-    b = random_operator(rsec, 0, 0, rng)
-    far = random_operator(lsec, 7, 1, rng)
-    rfar = random_operator(rsec, -7, 1, rng)
-    assert not far and not rfar
-    lops, rops = [a, far], [b, rfar]
-    pairs = [(0, 0, 0, 0, 1.5), (1, 1, 1, 1, 2.0)]
-    size = sum(lsec[i][2] * rsec[j][2] for i, j in su2.coupled_blocks(lsec, rsec, n, tS))
-    psi = rng.normal(size=size)
-    ref = oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs[:1], psi)
-    got = run(ctx, lsec, rsec, n, tS, lops, rops, pairs, psi)
-    assert np.abs(got - ref).max() <= TOL * np.abs(ref).max()
+    lsec, rsec, lops, rops, pairs, size, rng = case_ops(n, tS, 20, 6)
+    L, R = device_ops(lops), device_ops(rops)
+    x = torch.zeros(size, dtype=torch.float64, device="cuda")
+    other = Context(0)
+    try:
+        plan = other.su2_plan(lsec, rsec, n, tS, L, R, pairs)
+        h = plan.h
+        assert ctx.lib.dmrg_su2_plan_sigma(ctx.h, h, x.data_ptr(), x.data_ptr()) == INVALID_ARG
+        assert b"plan" in ctx.lib.dmrg_last_error(ctx.h)
+        plan.close()
+        assert other.lib.dmrg_su2_plan_sigma(other.h, h, x.data_ptr(), x.data_ptr()) == INVALID_ARG
+    finally:
+        other.close()
+
+
+def test_su2_sigma_cas89_102_sampled(ctx):
+    """The CAS(89,102)-shaped workload (S = 5/2, 2048 multiplets a side,
+    10,610 operator pairs of the spin-adapted Hamiltonian's structure,
+    random reduced blocks) through the plan the benchmark times, checked
+    on sampled output blocks: the largest and two drawn at random, each
+    computed by the oracle from every operator block that feeds it."""
+    import torch
+    w = cas89_102_workload()
+    lsec, rsec, n, tS = w["left_sectors"], w["right_sectors"], w["n"], w["two_s"]
+    print(f"su2 CAS(89,102): {len(w['pairs'])} pairs, psi {w['psi'].numel()}", flush=True)
+    with ctx.su2_plan(lsec, rsec, n, tS, w["left_ops"], w["right_ops"], w["pairs"]) as plan:
+        info = plan.info()
+        print(f"su2 CAS(89,102) plan: {info}", flush=True)
+        out = torch.full_like(w["psi"], float("nan"))
+        plan.sigma(w["psi"], out)
+        torch.cuda.synchronize()
+    got = unpack(lsec, rsec, n, tS, out.cpu().numpy())
+    psi = unpack(lsec, rsec, n, tS, w["psi"].cpu().numpy())
+    blocks = su2.coupled_blocks(lsec, rsec, n, tS)
+    sizes = [lsec[a][2] * rsec[b][2] for a, b in blocks]
+    rng = np.random.default_rng(7)
+    picks = [blocks[int(np.argmax(sizes))]] + [blocks[i] for i in rng.choice(len(blocks), 2, replace=False)]
+    lset, rset = {a for a, _ in picks}, {b for _, b in picks}
+
+    def restricted(ops, sectors, keep_out):
+        """{op: {(out, in): block}} for the blocks whose out sector is kept,
+        copied from the device in one gather."""
+        spans = []
+        for k, (blocks_k, _, base) in enumerate(ops):
+            for o, i, off in blocks_k:
+                if o in keep_out:
+                    spans.append((k, o, i, base + off, sectors[o][2], sectors[i][2]))
+        data = ops[0][1]
+        idx = np.concatenate([np.arange(s, s + d2 * d1) for _, _, _, s, d2, d1 in spans])
+        vals = data[torch.from_numpy(idx).cuda()].cpu().numpy()
+        res = [dict() for _ in ops]
+        pos = 0
+        for k, o, i, _, d2, d1 in spans:
+            res[k][(o, i)] = vals[pos:pos + d2 * d1].reshape(d2, d1)
+            pos += d2 * d1
+        return res
+
+    A = restricted(w["left_ops"], lsec, lset)
+    B = restricted(w["right_ops"], rsec, rset)
+    ref = su2.contract_scalar_products(lsec, rsec, n, tS, psi,
+                                       [(c, tk, pb, A[l], B[r]) for l, r, tk, pb, c in w["pairs"]])
+    assert info["psi_size"] == w["psi"].numel() and info["n_segments"] > 10 ** 6
+    for k in picks:
+        print(f"su2 CAS(89,102) block {k}: max|ref| {np.abs(ref[k]).max():.3e}", flush=True)
+        assert np.abs(ref[k]).max() > 1.0
+        assert np.abs(got[k] - ref[k]).max() <= TOL * np.abs(ref[k]).max()
