@@ -148,7 +148,6 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
   auto plan = std::make_unique<Su2Plan>();
   plan->psi_size = W.size;
   plan->psi.alloc((size_t)std::max<int64_t>(W.size, 1) * sizeof(double));
-  plan->sig.alloc((size_t)std::max<int64_t>(W.size, 1) * sizeof(double));
 
   // The stage-2 products: for each pair, each ket block (a, b) of psi, each
   // block A[a', a] of its left operator and B[b', b] of its right operator
@@ -212,47 +211,82 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
   plan->ws.alloc((size_t)std::max<int64_t>(plan->ws_doubles, 1) * sizeof(double));
   double* T = plan->ws.as<double>();
   const double* P = plan->psi.as<double>();
-  double* S = plan->sig.as<double>();
-  for (auto& ch : chunks) {
-    // stage 1: T(r, i, a) = psi[a, b] B_r[b', b]^T (d_a x d_b')
-    GemmBatch b1;
+  // stage-1 workspace offsets, and the stage-2 products of every output
+  // block (a', b') per chunk: W c (-1)^(p N_a) A[a', a] T
+  std::vector<std::map<std::pair<int, int>, std::vector<GemmSeg>>> outs(chunks.size());
+  size_t max_segs = 0;
+  for (size_t c = 0; c < chunks.size(); ++c) {
     int64_t off = 0;
-    for (int r = ch.first; r < ch.second; ++r) {
-      const dmrg_su2_operator& B = right_ops[r];
+    for (int r = chunks[c].first; r < chunks[c].second; ++r)
       for (auto& kv : need[r]) {
-        const int i = kv.first.first, a = kv.first.second;
-        const int b2 = B.out_sector[i], b = B.in_sector[i];
         kv.second = off;
-        const size_t s0 = b1.segs.size();
-        b1.segs.push_back({P + W.at(a, b), B.data + B.offset[i], W.rd[b], W.rd[b], W.rd[b], kTransB, 1.0});
-        b1.add_problem(T + off, W.rd[b2], W.ld[a], W.rd[b2], s0, s0 + 1, 0);
-        plan->flops1 += 2.0 * W.ld[a] * W.rd[b] * W.rd[b2];
-        off += (int64_t)W.ld[a] * W.rd[b2];
+        off += (int64_t)W.ld[kv.first.second] * W.rd[right_ops[r].out_sector[kv.first.first]];
       }
-    }
-    // stage 2: per output block (a', b'), the products W c (-1)^(p N_a) A[a', a] T
-    std::map<std::pair<int, int>, std::vector<GemmSeg>> outs;
-    for (int r = ch.first; r < ch.second; ++r)
+    size_t nseg = 0;
+    for (int r = chunks[c].first; r < chunks[c].second; ++r)
       for (const Prod& x : prods_of_r[r]) {
         const dmrg_su2_operator& A = left_ops[pairs[x.p].left_op];
         const dmrg_su2_operator& B = right_ops[r];
         const int a2 = A.out_sector[x.j], a = A.in_sector[x.j], b2 = B.out_sector[x.i];
         const int64_t to = need[r].at({x.i, a});
-        outs[{a2, b2}].push_back({A.data + A.offset[x.j], T + to, W.ld[a], W.rd[b2], W.ld[a], 0, x.scale});
+        outs[c][{a2, b2}].push_back({A.data + A.offset[x.j], T + to, W.ld[a], W.rd[b2], W.ld[a], 0, x.scale});
         plan->flops2 += 2.0 * W.ld[a2] * W.ld[a] * W.rd[b2];
+        ++nseg;
       }
+    max_segs = std::max(max_segs, nseg);
+  }
+  // Few output blocks with long product lists would leave most compute
+  // units idle: each output's list is split into up to n_parts pieces of
+  // about seg_per_part products, piece j summed into partial sum j, and the
+  // partial sums added in a fixed order at the end.
+  const size_t seg_per_part = std::max<size_t>(16, (max_segs + kSu2PartsPerLaunch - 1) / kSu2PartsPerLaunch);
+  int n_parts = 1;
+  for (auto& oc : outs)
+    for (auto& kv : oc) n_parts = std::max<int>(n_parts, (int)((kv.second.size() + seg_per_part - 1) / seg_per_part));
+  n_parts = (int)std::min<int64_t>(
+      {(int64_t)n_parts, (int64_t)kSu2MaxParts, std::max<int64_t>(1, kSu2PartialBudget / std::max<int64_t>(1, W.size))});
+  plan->n_parts = n_parts;
+  plan->part.alloc((size_t)std::max<int64_t>(1, (int64_t)n_parts * W.size) * sizeof(double));
+  {
+    std::vector<double> ones(n_parts, 1.0);
+    plan->ones.alloc(n_parts * sizeof(double));
+    DMRG_HIP(hipMemcpy(plan->ones.p, ones.data(), n_parts * sizeof(double), hipMemcpyHostToDevice));
+  }
+  double* Part = plan->part.as<double>();
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    // stage 1: T(r, i, a) = psi[a, b] B_r[b', b]^T (d_a x d_b')
+    GemmBatch b1;
+    for (int r = chunks[c].first; r < chunks[c].second; ++r) {
+      const dmrg_su2_operator& B = right_ops[r];
+      for (auto& kv : need[r]) {
+        const int i = kv.first.first, a = kv.first.second;
+        const int b2 = B.out_sector[i], b = B.in_sector[i];
+        const size_t s0 = b1.segs.size();
+        b1.segs.push_back({P + W.at(a, b), B.data + B.offset[i], W.rd[b], W.rd[b], W.rd[b], kTransB, 1.0});
+        b1.add_problem(T + kv.second, W.rd[b2], W.ld[a], W.rd[b2], s0, s0 + 1, 0);
+        plan->flops1 += 2.0 * W.ld[a] * W.rd[b] * W.rd[b2];
+      }
+    }
+    // stage 2: each output's products in contiguous pieces, one per partial sum
     GemmBatch b2;
-    for (auto& kv : outs) {
+    for (auto& kv : outs[c]) {
       const int a2 = kv.first.first, bb2 = kv.first.second;
-      const size_t s0 = b2.segs.size();
-      for (const GemmSeg& g : kv.second) b2.segs.push_back(g);
-      b2.add_problem(S + W.at(a2, bb2), W.rd[bb2], W.ld[a2], W.rd[bb2], s0, b2.segs.size(), 1);
+      const std::vector<GemmSeg>& g = kv.second;
+      const int parts = (int)std::min<size_t>(n_parts, (g.size() + seg_per_part - 1) / seg_per_part);
+      for (int j = 0; j < parts; ++j) {
+        const size_t lo = g.size() * j / parts, hi = g.size() * (j + 1) / parts;
+        const size_t s0 = b2.segs.size();
+        for (size_t q = lo; q < hi; ++q) b2.segs.push_back(g[q]);
+        b2.add_problem(Part + (int64_t)j * W.size + W.at(a2, bb2), W.rd[bb2], W.ld[a2], W.rd[bb2], s0,
+                       b2.segs.size(), 1);
+      }
     }
     plan->n_segments += (int64_t)(b1.segs.size() + b2.segs.size());
     plan->s1.emplace_back();
     upload_gemm(b1, plan->s1.back());
     plan->s2.emplace_back();
     upload_gemm(b2, plan->s2.back());
+    outs[c].clear();
   }
   (void)s;
   return plan;
@@ -263,14 +297,13 @@ void su2_run(Su2Plan& p, const double* psi, double* sigma, hipStream_t s) {
   if (p.psi_size == 0) return;
   // psi is copied into the plan first, so sigma may be the same buffer
   double* P = p.psi.as<double>();
-  double* S = p.sig.as<double>();
   DMRG_HIP(hipMemcpyAsync(P, psi, (size_t)p.psi_size * sizeof(double), hipMemcpyDeviceToDevice, s));
-  launch_fill(S, 0.0, p.psi_size, s);
+  launch_fill(p.part.as<double>(), 0.0, (int64_t)p.n_parts * p.psi_size, s);
   for (size_t c = 0; c < p.s1.size(); ++c) {
-    launch_gemm_f64(p.s1[c], s);
-    launch_gemm_f64(p.s2[c], s);
+    launch_gemm_f64(p.s1[c], s, 1);
+    launch_gemm_f64(p.s2[c], s, 2);
   }
-  DMRG_HIP(hipMemcpyAsync(sigma, S, (size_t)p.psi_size * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_lincomb(sigma, p.part.as<double>(), p.psi_size, p.n_parts, p.ones.as<double>(), p.psi_size, 0.0, s);
 }
 
 }  // namespace dmrg

@@ -19,14 +19,24 @@ int64_t su2_psi_size(const dmrg_su2_window& w);
 
 // Device descriptors of one window's spin-adapted sigma: per workspace
 // chunk a stage-1 launch (T = psi B^T for the chunk's right operators) and a
-// stage-2 launch (sigma += W c A T), on plan-owned psi, sigma and workspace.
+// stage-2 launch (partial sums of sigma += W c A T), on plan-owned psi,
+// partial sums and workspace; sigma is the sum of the partial sums.
 struct Su2Plan {
   int64_t psi_size = 0;
-  DevBuf psi, sig, ws;
+  DevBuf psi, ws;
+  DevBuf part, ones;  // n_parts partial sums of sigma (psi_size each), and n_parts ones
+  int n_parts = 1;
   std::vector<DevGemm> s1, s2;
   int64_t n_segments = 0, ws_doubles = 0;
   double flops1 = 0, flops2 = 0;
 };
+
+// Stage-2 product lists are split so that a launch has about this many
+// pieces, into at most kSu2MaxParts partial sums of at most
+// kSu2PartialBudget doubles in all.
+constexpr size_t kSu2PartsPerLaunch = 2048;
+constexpr int kSu2MaxParts = 256;
+constexpr int64_t kSu2PartialBudget = (int64_t)1 << 27;
 
 // Builds the plan (host checks as dmrg_su2_sigma; ws_budget in doubles).
 std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, const dmrg_su2_operator* left_ops,
