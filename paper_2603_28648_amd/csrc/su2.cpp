@@ -19,6 +19,7 @@
 #include "su2.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <tuple>
@@ -239,7 +240,9 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
   // units idle: each output's list is split into up to n_parts pieces of
   // about seg_per_part products, piece j summed into partial sum j, and the
   // partial sums added in a fixed order at the end.
-  const size_t seg_per_part = std::max<size_t>(16, (max_segs + kSu2PartsPerLaunch - 1) / kSu2PartsPerLaunch);
+  size_t per_launch = kSu2PartsPerLaunch;
+  if (const char* e = std::getenv("DMRG_SU2_PARTS")) per_launch = std::max<long long>(1, std::atoll(e));
+  const size_t seg_per_part = std::max<size_t>(16, (max_segs + per_launch - 1) / per_launch);
   int n_parts = 1;
   for (auto& oc : outs)
     for (auto& kv : oc) n_parts = std::max<int>(n_parts, (int)((kv.second.size() + seg_per_part - 1) / seg_per_part));

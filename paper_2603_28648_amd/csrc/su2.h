@@ -32,9 +32,9 @@ struct Su2Plan {
 };
 
 // Stage-2 product lists are split so that a launch has about this many
-// pieces, into at most kSu2MaxParts partial sums of at most
-// kSu2PartialBudget doubles in all.
-constexpr size_t kSu2PartsPerLaunch = 2048;
+// pieces (DMRG_SU2_PARTS overrides), into at most kSu2MaxParts partial sums
+// of at most kSu2PartialBudget doubles in all.
+constexpr size_t kSu2PartsPerLaunch = 8192;
 constexpr int kSu2MaxParts = 256;
 constexpr int64_t kSu2PartialBudget = (int64_t)1 << 27;
 
