@@ -9,13 +9,13 @@
 //   W = (-1)^(S_a + S_b' + S + k) sqrt((2 S_a' + 1)(2 S_b' + 1) / (2k + 1)) {S_a S_b S; S_b' S_a' k}
 // for reduced matrices in the Clebsch-Gordan convention of the Wigner-Eckart
 // theorem (the 6j symbol from Racah's formula).  The two stages are the ones
-// of the U(1) sigma: stage 1 forms T = psi[a, b] B[b', b]^T once per right
-// operator block and left sector (NT products), stage 2 accumulates
-// W c (-1)^(p N_a) A[a', a] T into each output block (NN products), every
-// output block one problem of the grouped GEMM with its segments.  A plan
-// keeps both stages' descriptors per chunk of right operators, whose stage-1
-// products fit the workspace budget; stage 1 only forms the products some
-// pair's stage 2 reads.
+// of the U(1) sigma: stage 1 forms T = psi[., b] B[b', b]^T once per right
+// operator block, over the blocks (a, b) of its right sector stacked by a
+// (NT products), stage 2 accumulates W c (-1)^(p N_a) A[a', a] T[a] into
+// each output block (NN products).  A plan keeps both stages' descriptors per
+// chunk of right operators, whose stage-1 products fit the workspace budget;
+// stage 1 only forms the rows some pair's stage 2 reads, and long stage-2
+// product lists are split over partial sums of sigma.
 #include "su2.h"
 
 #include <cmath>
@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "common.h"
+#include "engine.h"
 #include "gemm.h"
 
 namespace dmrg {
@@ -183,16 +184,38 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
           }
       }
   }
-  // Stage-1 products needed per right operator: (block i of B, left sector a)
-  // -> workspace rows; chunks of right operators within the budget.
-  std::vector<std::map<std::pair<int, int>, int64_t>> need(n_right_ops);
+  // psi regrouped by right sector inside the plan: for each b the coupled
+  // blocks (a, b) stacked by a into one (M_b x d_b) matrix, block (a, b) at
+  // row rowoff(a, b); stage 1 then multiplies every needed row of a right
+  // sector by a block of B in one product.
+  std::vector<int64_t> boff(nr + 1, 0), rowoff((size_t)nl * nr, -1), mb(nr, 0);
+  for (int b = 0; b < nr; ++b) {
+    for (int a = 0; a < nl; ++a)
+      if (W.at(a, b) >= 0) {
+        rowoff[(size_t)a * nr + b] = mb[b];
+        mb[b] += W.ld[a];
+      }
+    boff[b + 1] = boff[b] + mb[b] * W.rd[b];
+  }
+  // Stage-1 products per right operator: block i of B -> the row range of
+  // psi_b it multiplies (from the first to the last needed left sector) and
+  // the workspace offset of T(r, i) (M_b x d_b').
+  struct S1 {
+    int64_t lo = -1, hi = -1, off = 0;
+  };
+  std::vector<std::map<int, S1>> need(n_right_ops);
   std::vector<int64_t> rsize(n_right_ops, 0);
-  for (int r = 0; r < n_right_ops; ++r)
+  for (int r = 0; r < n_right_ops; ++r) {
     for (const Prod& x : prods_of_r[r]) {
       const int a = left_ops[pairs[x.p].left_op].in_sector[x.j];
-      const int b2 = right_ops[r].out_sector[x.i];
-      if (need[r].emplace(std::make_pair(x.i, a), 0).second) rsize[r] += (int64_t)W.ld[a] * W.rd[b2];
+      const int b = right_ops[r].in_sector[x.i];
+      const int64_t r0 = rowoff[(size_t)a * nr + b], r1 = r0 + W.ld[a];
+      S1& e = need[r][x.i];
+      e.lo = e.lo < 0 ? r0 : std::min(e.lo, r0);
+      e.hi = std::max(e.hi, r1);
     }
+    for (auto& kv : need[r]) rsize[r] += mb[right_ops[r].in_sector[kv.first]] * W.rd[right_ops[r].out_sector[kv.first]];
+  }
   std::vector<std::pair<int, int>> chunks;
   {
     int r0 = 0;
@@ -211,7 +234,21 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
   }
   plan->ws.alloc((size_t)std::max<int64_t>(plan->ws_doubles, 1) * sizeof(double));
   double* T = plan->ws.as<double>();
+  plan->psi_b.alloc((size_t)std::max<int64_t>(W.size, 1) * sizeof(double));
   const double* P = plan->psi.as<double>();
+  double* Pb = plan->psi_b.as<double>();
+  {
+    std::vector<CopyTask> tasks;
+    for (int a = 0; a < nl; ++a)
+      for (int b = 0; b < nr; ++b)
+        if (W.at(a, b) >= 0)
+          tasks.push_back({P + W.at(a, b), Pb + boff[b] + rowoff[(size_t)a * nr + b] * W.rd[b], W.ld[a], W.rd[b],
+                           W.rd[b], W.rd[b]});
+    plan->n_regroup = (int)tasks.size();
+    plan->regroup.alloc(std::max<size_t>(1, tasks.size()) * sizeof(CopyTask));
+    if (!tasks.empty())
+      DMRG_HIP(hipMemcpy(plan->regroup.p, tasks.data(), tasks.size() * sizeof(CopyTask), hipMemcpyHostToDevice));
+  }
   // stage-1 workspace offsets, and the stage-2 products of every output
   // block (a', b') per chunk: W c (-1)^(p N_a) A[a', a] T
   std::vector<std::map<std::pair<int, int>, std::vector<GemmSeg>>> outs(chunks.size());
@@ -220,16 +257,16 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
     int64_t off = 0;
     for (int r = chunks[c].first; r < chunks[c].second; ++r)
       for (auto& kv : need[r]) {
-        kv.second = off;
-        off += (int64_t)W.ld[kv.first.second] * W.rd[right_ops[r].out_sector[kv.first.first]];
+        kv.second.off = off;
+        off += mb[right_ops[r].in_sector[kv.first]] * W.rd[right_ops[r].out_sector[kv.first]];
       }
     size_t nseg = 0;
     for (int r = chunks[c].first; r < chunks[c].second; ++r)
       for (const Prod& x : prods_of_r[r]) {
         const dmrg_su2_operator& A = left_ops[pairs[x.p].left_op];
         const dmrg_su2_operator& B = right_ops[r];
-        const int a2 = A.out_sector[x.j], a = A.in_sector[x.j], b2 = B.out_sector[x.i];
-        const int64_t to = need[r].at({x.i, a});
+        const int a2 = A.out_sector[x.j], a = A.in_sector[x.j], b2 = B.out_sector[x.i], b = B.in_sector[x.i];
+        const int64_t to = need[r].at(x.i).off + rowoff[(size_t)a * nr + b] * W.rd[b2];
         outs[c][{a2, b2}].push_back({A.data + A.offset[x.j], T + to, W.ld[a], W.rd[b2], W.ld[a], 0, x.scale});
         plan->flops2 += 2.0 * W.ld[a2] * W.ld[a] * W.rd[b2];
         ++nseg;
@@ -257,17 +294,20 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
   }
   double* Part = plan->part.as<double>();
   for (size_t c = 0; c < chunks.size(); ++c) {
-    // stage 1: T(r, i, a) = psi[a, b] B_r[b', b]^T (d_a x d_b')
+    // stage 1: rows [lo, hi) of T(r, i) = psi_b B_r[i]^T (M_b x d_b'),
+    // psi_b holding the blocks (a, b) stacked by a
     GemmBatch b1;
     for (int r = chunks[c].first; r < chunks[c].second; ++r) {
       const dmrg_su2_operator& B = right_ops[r];
       for (auto& kv : need[r]) {
-        const int i = kv.first.first, a = kv.first.second;
+        const int i = kv.first;
+        const S1& e = kv.second;
         const int b2 = B.out_sector[i], b = B.in_sector[i];
         const size_t s0 = b1.segs.size();
-        b1.segs.push_back({P + W.at(a, b), B.data + B.offset[i], W.rd[b], W.rd[b], W.rd[b], kTransB, 1.0});
-        b1.add_problem(T + kv.second, W.rd[b2], W.ld[a], W.rd[b2], s0, s0 + 1, 0);
-        plan->flops1 += 2.0 * W.ld[a] * W.rd[b] * W.rd[b2];
+        b1.segs.push_back({Pb + boff[b] + e.lo * W.rd[b], B.data + B.offset[i], W.rd[b], W.rd[b], W.rd[b],
+                           kTransB, 1.0});
+        b1.add_problem(T + e.off + e.lo * W.rd[b2], W.rd[b2], (int)(e.hi - e.lo), W.rd[b2], s0, s0 + 1, 0);
+        plan->flops1 += 2.0 * (e.hi - e.lo) * W.rd[b] * W.rd[b2];
       }
     }
     // stage 2: each output's products in contiguous pieces, one per partial sum
@@ -301,6 +341,7 @@ void su2_run(Su2Plan& p, const double* psi, double* sigma, hipStream_t s) {
   // psi is copied into the plan first, so sigma may be the same buffer
   double* P = p.psi.as<double>();
   DMRG_HIP(hipMemcpyAsync(P, psi, (size_t)p.psi_size * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_copy_tasks(p.regroup.as<CopyTask>(), p.n_regroup, false, s);
   launch_fill(p.part.as<double>(), 0.0, (int64_t)p.n_parts * p.psi_size, s);
   for (size_t c = 0; c < p.s1.size(); ++c) {
     launch_gemm_f64(p.s1[c], s, 1);

@@ -23,7 +23,9 @@ int64_t su2_psi_size(const dmrg_su2_window& w);
 // partial sums and workspace; sigma is the sum of the partial sums.
 struct Su2Plan {
   int64_t psi_size = 0;
-  DevBuf psi, ws;
+  DevBuf psi, psi_b, ws;  // psi as given, psi regrouped by right sector, stage-1 workspace
+  DevBuf regroup;          // copy tasks psi -> psi_b
+  int n_regroup = 0;
   DevBuf part, ones;  // n_parts partial sums of sigma (psi_size each), and n_parts ones
   int n_parts = 1;
   std::vector<DevGemm> s1, s2;
