@@ -223,3 +223,24 @@ def test_su2_sigma_cas89_102_sampled(ctx):
         print(f"su2 CAS(89,102) block {k}: max|ref| {np.abs(ref[k]).max():.3e}", flush=True)
         assert np.abs(ref[k]).max() > 1.0
         assert np.abs(got[k] - ref[k]).max() <= TOL * np.abs(ref[k]).max()
+
+
+def test_su2_operator_past_its_tensor_is_refused(ctx):
+    """The binding checks every block against its data tensor before the
+    library sees the pointers (no kernel runs)."""
+    import torch
+    lsec, rsec = [(1, 1, 4)], [(1, 1, 3)]
+    short = torch.zeros(15, dtype=torch.float64, device="cuda")  # a 4 x 4 block needs 16
+    ok = torch.zeros(9, dtype=torch.float64, device="cuda")
+    psi = torch.zeros(12, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.su2_sigma(lsec, rsec, 2, 0, [([(0, 0, 0)], short)], [([(0, 0, 0)], ok)], [(0, 0, 0, 0, 1.0)],
+                      psi, psi.clone())
+    full = torch.zeros(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):  # the right block starts one element in: it ends past the tensor
+        ctx.su2_sigma(lsec, rsec, 2, 0, [([(0, 0, 0)], full)], [([(0, 0, 0)], ok, 1)], [(0, 0, 0, 0, 1.0)],
+                      psi, psi.clone())
+    out = psi.clone()
+    ctx.su2_sigma(lsec, rsec, 2, 0, [([(0, 0, 0)], full)], [([(0, 0, 0)], ok, 0)], [(0, 0, 0, 0, 1.0)],
+                  psi, out)
+    assert torch.all(out == 0)
