@@ -169,6 +169,11 @@ def su2_bench(ctx, steps):
         plan.close()
     flops = info["flops_stage1"] + info["flops_stage2"]
     tflops = flops / (ms * 1e-3) / 1e12
+    csrc = os.path.join(ROOT, "paper_2603_28648_amd", "csrc")
+    pt = profiled_traffic("k_gemm_f64_su2_cas89_102_D2048.md",
+                          [os.path.join(csrc, "kernels.hip"), os.path.join(csrc, "su2.cpp")],
+                          "su2_tiles", os.environ.get("DMRG_SU2_TILE", "128x64,128x64"))
+    traffic = pt[0] / pt[1] if pt else None  # bytes per launch
     leg = {"workload": "cas89_102 S=5/2: 51|51 orbitals, 2048 multiplets a side, "
                        f"{len(w['pairs'])} operator pairs, random reduced blocks",
            "psi_size": info["psi_size"], "pairs": len(w["pairs"]),
@@ -178,7 +183,9 @@ def su2_bench(ctx, steps):
            "flops_stages": [info["flops_stage1"], info["flops_stage2"]],
            "gen_s": round(t_gen, 2), "plan_s": round(t_plan, 2), "ms": ms, "tflops": tflops,
            "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_TFLOPS["fp64"],
-                        "unit": "TFLOP/s", "frac": tflops / PEAK_TFLOPS["fp64"],
+                        "unit": "TFLOP/s", "frac": tflops / PEAK_TFLOPS["fp64"], "traffic": traffic,
+                        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                        "launches_per_step": 2 * info["n_chunks"],
                         "kernel": "k_gemm_f64 (stage-1 and stage-2 launches of every chunk)"}}
     log(f"[bench] su2 sigma (CAS(89,102) S=5/2, {len(w['pairs'])} pairs, {info['n_chunks']} chunks, "
         f"{info['n_segments']} block products): {ms:.1f} ms, {tflops:.1f} TFLOP/s FP64 "
