@@ -167,6 +167,21 @@ def su2_bench(ctx, steps):
         ms = (time.perf_counter() - t0) / steps * 1e3
     finally:
         plan.close()
+    # split-BF16x3 plan of the same workload, against the FP64 result
+    plan3 = ctx.su2_plan(w["left_sectors"], w["right_sectors"], w["n"], w["two_s"], w["left_ops"],
+                         w["right_ops"], w["pairs"], precision="bf16x3")
+    try:
+        out3 = torch.empty_like(w["psi"])
+        plan3.sigma(w["psi"], out3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan3.sigma(w["psi"], out3)
+        torch.cuda.synchronize()
+        ms3 = (time.perf_counter() - t0) / steps * 1e3
+    finally:
+        plan3.close()
+    rel3 = float((torch.linalg.norm(out3 - out) / torch.linalg.norm(out)).item())
     flops = info["flops_stage1"] + info["flops_stage2"]
     tflops = flops / (ms * 1e-3) / 1e12
     csrc = os.path.join(ROOT, "paper_2603_28648_amd", "csrc")
@@ -182,6 +197,8 @@ def su2_bench(ctx, steps):
            "workspace_gb": info["workspace_bytes"] / 1e9, "flops": flops,
            "flops_stages": [info["flops_stage1"], info["flops_stage2"]],
            "gen_s": round(t_gen, 2), "plan_s": round(t_plan, 2), "ms": ms, "tflops": tflops,
+           "bf16x3": {"ms": ms3, "tflops": flops / (ms3 * 1e-3) / 1e12, "speedup_vs_fp64": ms / ms3,
+                      "sigma_rel_err_vs_fp64": rel3},
            "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_TFLOPS["fp64"],
                         "unit": "TFLOP/s", "frac": tflops / PEAK_TFLOPS["fp64"], "traffic": traffic,
                         "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -189,7 +206,8 @@ def su2_bench(ctx, steps):
                         "kernel": "k_gemm_f64 (stage-1 and stage-2 launches of every chunk)"}}
     log(f"[bench] su2 sigma (CAS(89,102) S=5/2, {len(w['pairs'])} pairs, {info['n_chunks']} chunks, "
         f"{info['n_segments']} block products): {ms:.1f} ms, {tflops:.1f} TFLOP/s FP64 "
-        f"({100 * tflops / PEAK_TFLOPS['fp64']:.1f}% of peak); plan {t_plan:.1f} s, inputs {t_gen:.1f} s")
+        f"({100 * tflops / PEAK_TFLOPS['fp64']:.1f}% of peak); plan {t_plan:.1f} s, inputs {t_gen:.1f} s; "
+        f"split-BF16x3 {ms3:.1f} ms ({ms / ms3:.2f}x), |dsigma|/|sigma| = {rel3:.2e}")
     del w
     torch.cuda.empty_cache()
     return leg

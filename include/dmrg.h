@@ -422,13 +422,17 @@ dmrg_status dmrg_su2_sigma(dmrg_ctx ctx, const dmrg_su2_window* window, int32_t 
  * plan lives.  It owns device copies of psi and sigma and the workspace.
  * A plan belongs to its context: it is used and destroyed through that
  * context, and dmrg_destroy releases plans still alive (their handles then
- * become invalid).  Errors: those of dmrg_su2_sigma; DMRG_ERR_OOM when
- * device memory runs out. */
+ * become invalid).  precision: DMRG_FP64, or DMRG_BF16X3 (split-BF16
+ * products with FP32 accumulation, flushed into FP64 per segment: the
+ * plan packs the operator blocks once into BF16 hi/lo copies, rows padded
+ * to 8 elements, and psi on every call; the Mixed precision section).
+ * Errors: those of dmrg_su2_sigma; DMRG_ERR_INVALID_ARG for another
+ * precision; DMRG_ERR_OOM when device memory runs out. */
 typedef struct dmrg_su2_plan_s* dmrg_su2_plan;
 dmrg_status dmrg_su2_plan_create(dmrg_ctx ctx, const dmrg_su2_window* window, int32_t n_left_ops,
                                  const dmrg_su2_operator* left_ops, int32_t n_right_ops,
                                  const dmrg_su2_operator* right_ops, int32_t n_pairs,
-                                 const dmrg_su2_pair* pairs, dmrg_su2_plan* plan);
+                                 const dmrg_su2_pair* pairs, int32_t precision, dmrg_su2_plan* plan);
 
 /* sigma = the plan's contraction of psi (device pointers of psi_size
  * elements, caller-owned; sigma may be psi itself).  Stream-ordered on the
@@ -443,7 +447,7 @@ typedef struct {
   int32_t n_chunks;        /* workspace chunks (stage-1 + stage-2 launch pairs) */
   int32_t pad;
   int64_t n_segments;      /* block products of both stages */
-  int64_t workspace_bytes; /* stage-1 workspace (the largest chunk) */
+  int64_t workspace_bytes; /* stage-1 workspace (the largest chunk; BF16 hi + lo for DMRG_BF16X3) */
   double flops_stage1;     /* 2 d_a d_b d_b' per stage-1 product */
   double flops_stage2;     /* 2 d_a' d_a d_b' per stage-2 product */
 } dmrg_su2_info;

@@ -146,7 +146,7 @@ EXPORTS = {
     "dmrg_su2_plan_create": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Su2Window), ctypes.c_int32,
                                               ctypes.POINTER(Su2Operator), ctypes.c_int32,
                                               ctypes.POINTER(Su2Operator), ctypes.c_int32, ctypes.POINTER(Su2Pair),
-                                              ctypes.POINTER(ctypes.c_void_p)]),
+                                              ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "dmrg_su2_plan_sigma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_su2_plan_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Su2Info)]),
     "dmrg_su2_plan_destroy": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -615,13 +615,14 @@ class Context:
             if v.numel() != n:
                 raise ValueError(f"expected {n} elements, got {v.numel()}")
 
-    def su2_plan(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs):
-        """dmrg_su2_plan_create: a Su2Plan (arguments as in _su2_args).  The
-        operator tensors must outlive the plan."""
+    def su2_plan(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, precision="fp64"):
+        """dmrg_su2_plan_create: a Su2Plan (arguments as in _su2_args;
+        precision "fp64" or "bf16x3").  The operator tensors must outlive the
+        plan."""
         keep = []
         args = self._su2_args(left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, keep)
         h = ctypes.c_void_p()
-        self._check(self.lib.dmrg_su2_plan_create(self.h, *args, ctypes.byref(h)), self.h)
+        self._check(self.lib.dmrg_su2_plan_create(self.h, *args, PRECISIONS[precision], ctypes.byref(h)), self.h)
         return Su2Plan(self, h)
 
     def debug_diag(self, out):

@@ -595,8 +595,8 @@ dmrg_status dmrg_su2_sigma(dmrg_ctx c, const dmrg_su2_window* window, int32_t n_
   if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
   return guarded(c, [&]() -> dmrg_status {
     DMRG_REQUIRE(window, kErrInvalidArg, "su2_sigma: NULL window");
-    auto plan = su2_plan(*window, n_left_ops, left_ops, n_right_ops, right_ops, n_pairs, pairs, c->ws_budget,
-                         c->stream);
+    auto plan = su2_plan(*window, n_left_ops, left_ops, n_right_ops, right_ops, n_pairs, pairs, DMRG_FP64,
+                         c->ws_budget, c->stream);
     su2_run(*plan, psi, sigma, c->stream);
     DMRG_HIP(hipStreamSynchronize(c->stream));  // the plan's buffers are released on return
     return kOk;
@@ -606,13 +606,13 @@ dmrg_status dmrg_su2_sigma(dmrg_ctx c, const dmrg_su2_window* window, int32_t n_
 dmrg_status dmrg_su2_plan_create(dmrg_ctx c, const dmrg_su2_window* window, int32_t n_left_ops,
                                  const dmrg_su2_operator* left_ops, int32_t n_right_ops,
                                  const dmrg_su2_operator* right_ops, int32_t n_pairs,
-                                 const dmrg_su2_pair* pairs, dmrg_su2_plan* out) {
+                                 const dmrg_su2_pair* pairs, int32_t precision, dmrg_su2_plan* out) {
   if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
   return guarded(c, [&]() -> dmrg_status {
     DMRG_REQUIRE(window && out, kErrInvalidArg, "su2_plan_create: NULL pointer");
     *out = nullptr;
-    auto plan = su2_plan(*window, n_left_ops, left_ops, n_right_ops, right_ops, n_pairs, pairs, c->ws_budget,
-                         c->stream);
+    auto plan = su2_plan(*window, n_left_ops, left_ops, n_right_ops, right_ops, n_pairs, pairs, precision,
+                         c->ws_budget, c->stream);
     dmrg_su2_plan h = new dmrg_su2_plan_s;
     c->su2_plans[h] = std::move(plan);
     *out = h;
@@ -641,9 +641,10 @@ dmrg_status dmrg_su2_plan_info(dmrg_ctx c, dmrg_su2_plan h, dmrg_su2_info* out) 
     const Su2Plan& p = su2_of(c, h);
     *out = dmrg_su2_info{};
     out->psi_size = p.psi_size;
-    out->n_chunks = (int32_t)p.s1.size();
+    const bool x3 = p.precision == DMRG_BF16X3;
+    out->n_chunks = (int32_t)(x3 ? p.s1b.size() : p.s1.size());
     out->n_segments = p.n_segments;
-    out->workspace_bytes = p.ws_doubles * (int64_t)sizeof(double);
+    out->workspace_bytes = p.ws_doubles * (int64_t)(x3 ? 2 * sizeof(uint16_t) : sizeof(double));
     out->flops_stage1 = p.flops1;
     out->flops_stage2 = p.flops2;
     return kOk;

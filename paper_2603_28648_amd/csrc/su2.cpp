@@ -30,6 +30,7 @@
 #include "common.h"
 #include "engine.h"
 #include "gemm.h"
+#include "gemm_bf16.h"
 
 namespace dmrg {
 
@@ -102,6 +103,19 @@ std::vector<std::vector<int>> by_in_sector(const dmrg_su2_operator& o, int ns) {
   return v;
 }
 
+// A stage-2 product: pair, block of its right operator B, block of its left
+// operator A, and the scale c (-1)^(p N_a) W.
+struct Prod {
+  int p, i, j;
+  double scale;
+};
+// The stage-1 product of a right-operator block: rows [lo, hi) of psi_b and
+// the workspace offset of T(r, i).
+struct S1 {
+  int64_t lo = -1, hi = -1, off = 0;
+};
+inline int64_t pad8(int64_t x) { return (x + 7) & ~(int64_t)7; }
+
 // Output tiles (rows, cols) of the two stages: 128 x 64 with eight waves
 // for both, measured at the CAS(89,102)-shaped workload (ms per sigma):
 // 170.7, against 178.3 with 64 x 64, 177.3 with 128 x 64 for stage 1 only,
@@ -146,9 +160,142 @@ double wigner_6j(int tj1, int tj2, int tj3, int tj4, int tj5, int tj6) {
 
 int64_t su2_psi_size(const dmrg_su2_window& w) { return parse(w).size; }
 
+namespace {
+
+// The split-BF16x3 descriptors: operator blocks packed once into
+// k-contiguous BF16 hi/lo planes (rows padded to 8), psi_b packed per call,
+// stage 1 writing T(r, i)^T (d_b' x M_b, BF16 hi/lo) and stage 2 reading the
+// d_a columns of block a from it; every product is NT on 16-byte aligned
+// rows, as the BF16 kernel needs.
+void build_bf16(Su2Plan& plan, const Window& W, const dmrg_su2_operator* left_ops,
+                const dmrg_su2_operator* right_ops, const std::vector<std::vector<Prod>>& prods_of_r,
+                const dmrg_su2_pair* pairs, const std::vector<std::map<int, S1>>& need,
+                const std::vector<std::pair<int, int>>& chunks, const std::vector<int64_t>& mb,
+                const std::vector<int64_t>& boff, const std::vector<int64_t>& rowoff, size_t seg_per_part,
+                hipStream_t s) {
+  const int nr = (int)W.rn.size();
+  // packed operator blocks: (op, block) -> element offset of its hi plane
+  std::vector<PackOp> ops;
+  int64_t chunks8 = 0, total = 0;
+  auto add = [&](const double* src, int rows, int k) {
+    const int kp = (int)pad8(k);
+    ops.push_back({src, total, chunks8, k, rows, k, kp, 0, 0});
+    const int64_t at = total;
+    total += 2 * (int64_t)rows * kp;
+    chunks8 += (int64_t)rows * kp / 8;
+    return at;
+  };
+  std::map<std::pair<int, int>, int64_t> lpos, rpos;  // (op, block) -> packed offset
+  for (int r = 0; r < (int)prods_of_r.size(); ++r)
+    for (const Prod& x : prods_of_r[r]) {
+      const int l = pairs[x.p].left_op;
+      const dmrg_su2_operator& A = left_ops[l];
+      if (!lpos.count({l, x.j}))
+        lpos[{l, x.j}] = add(A.data + A.offset[x.j], W.ld[A.out_sector[x.j]], W.ld[A.in_sector[x.j]]);
+    }
+  const int64_t lsize = total;
+  for (int r = 0; r < (int)need.size(); ++r)
+    for (auto& kv : need[r]) {
+      const dmrg_su2_operator& B = right_ops[r];
+      rpos[{r, kv.first}] = add(B.data + B.offset[kv.first], W.rd[B.out_sector[kv.first]], W.rd[B.in_sector[kv.first]]);
+    }
+  plan.opk.alloc((size_t)std::max<int64_t>(total, 8) * sizeof(uint16_t));
+  uint16_t* K = plan.opk.as<uint16_t>();
+  {
+    DevBuf d(std::max<size_t>(1, ops.size()) * sizeof(PackOp));
+    if (!ops.empty()) {
+      DMRG_HIP(hipMemcpy(d.p, ops.data(), ops.size() * sizeof(PackOp), hipMemcpyHostToDevice));
+      launch_pack_bf16(d.as<PackOp>(), (int)ops.size(), chunks8, K, s);
+    }
+    DMRG_HIP(hipStreamSynchronize(s));
+  }
+  (void)lsize;
+  // psi_b packed per call: one pass over every right sector's M_b x d_b matrix
+  {
+    std::vector<PackOp> pops;
+    int64_t c8 = 0, at = 0;
+    std::vector<int64_t> poff(nr, 0);
+    for (int b = 0; b < nr; ++b) {
+      if (mb[b] == 0) continue;
+      const int kp = (int)pad8(W.rd[b]);
+      poff[b] = at;
+      pops.push_back({plan.psi_b.as<double>() + boff[b], at, c8, W.rd[b], (int)mb[b], W.rd[b], kp, 0, 0});
+      at += 2 * mb[b] * kp;
+      c8 += mb[b] * kp / 8;
+    }
+    plan.psi_pack.alloc((size_t)std::max<int64_t>(at, 8) * sizeof(uint16_t));
+    plan.psi_pack_ops.alloc(std::max<size_t>(1, pops.size()) * sizeof(PackOp));
+    if (!pops.empty())
+      DMRG_HIP(hipMemcpy(plan.psi_pack_ops.p, pops.data(), pops.size() * sizeof(PackOp), hipMemcpyHostToDevice));
+    plan.n_psi_pack = (int)pops.size();
+    plan.psi_pack_chunks = c8;
+    plan.psi_poff = poff;
+  }
+  const uint16_t* Q = plan.psi_pack.as<uint16_t>();
+  plan.wsk.alloc((size_t)std::max<int64_t>(2 * plan.ws_doubles, 8) * sizeof(uint16_t));
+  uint16_t* T = plan.wsk.as<uint16_t>();
+  const int64_t tlo = plan.ws_doubles;  // lo plane of the workspace
+  double* Part = plan.part.as<double>();
+  const int n_parts = plan.n_parts;
+  for (size_t c = 0; c < chunks.size(); ++c) {
+    // stage 1: columns [lo, pad8(hi)) of T(r, i)^T = B_r[i] psi_b^T (d_b' x M_b)
+    GemmBatchB b1;
+    b1.shape = kShape64x128;
+    for (int r = chunks[c].first; r < chunks[c].second; ++r) {
+      const dmrg_su2_operator& B = right_ops[r];
+      for (auto& kv : need.at(r)) {
+        const int i = kv.first;
+        const S1& e = kv.second;
+        const int b2 = B.out_sector[i], b = B.in_sector[i];
+        const int64_t kp = pad8(W.rd[b]);
+        const size_t s0 = b1.segs.size();
+        b1.segs.push_back({K + rpos.at({r, i}), Q + plan.psi_poff[b] + e.lo * kp, (int64_t)W.rd[b2] * kp,
+                           mb[b] * kp, (int)kp, (int)kp, W.rd[b], kTransB, 1.0});
+        b1.add_problem(T + e.off + e.lo, tlo, (int)mb[b], W.rd[b2], (int)(pad8(e.hi) - e.lo), s0, s0 + 1, 0);
+      }
+    }
+    // stage 2: as the FP64 plan, on the packed operands
+    std::map<std::pair<int, int>, std::vector<GemmSegB>> outs;
+    for (int r = chunks[c].first; r < chunks[c].second; ++r)
+      for (const Prod& x : prods_of_r[r]) {
+        const int l = pairs[x.p].left_op;
+        const dmrg_su2_operator& A = left_ops[l];
+        const dmrg_su2_operator& B = right_ops[r];
+        const int a2 = A.out_sector[x.j], a = A.in_sector[x.j], b2 = B.out_sector[x.i], b = B.in_sector[x.i];
+        const int64_t kp = pad8(W.ld[a]);
+        const S1& e = need[r].at(x.i);
+        outs[{a2, b2}].push_back({K + lpos.at({l, x.j}), T + e.off + rowoff[(size_t)a * nr + b],
+                                  (int64_t)W.ld[a2] * kp, tlo, (int)kp, (int)mb[b], W.ld[a], kTransB, x.scale});
+      }
+    GemmBatchB b2;
+    b2.shape = kShape64x64;
+    for (auto& kv : outs) {
+      const int a2 = kv.first.first, bb2 = kv.first.second;
+      const std::vector<GemmSegB>& g = kv.second;
+      const int parts = (int)std::min<size_t>(n_parts, (g.size() + seg_per_part - 1) / seg_per_part);
+      for (int j = 0; j < parts; ++j) {
+        const size_t lo = g.size() * j / parts, hi = g.size() * (j + 1) / parts;
+        const size_t s0 = b2.segs.size();
+        for (size_t q = lo; q < hi; ++q) b2.segs.push_back(g[q]);
+        b2.add_problem(Part + (int64_t)j * W.size + W.at(a2, bb2), 0, W.rd[bb2], W.ld[a2], W.rd[bb2], s0,
+                       b2.segs.size(), 1);
+      }
+    }
+    plan.n_segments += (int64_t)(b1.segs.size() + b2.segs.size());
+    plan.s1b.emplace_back();
+    upload_gemm_bf16(b1, plan.s1b.back());
+    plan.s2b.emplace_back();
+    upload_gemm_bf16(b2, plan.s2b.back());
+  }
+}
+
+}  // namespace
+
 std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, const dmrg_su2_operator* left_ops,
                                   int n_right_ops, const dmrg_su2_operator* right_ops, int n_pairs,
-                                  const dmrg_su2_pair* pairs, int64_t ws_budget, hipStream_t s) {
+                                  const dmrg_su2_pair* pairs, int precision, int64_t ws_budget, hipStream_t s) {
+  DMRG_REQUIRE(precision == DMRG_FP64 || precision == DMRG_BF16X3, kErrInvalidArg,
+               "su2: precision must be DMRG_FP64 or DMRG_BF16X3");
   const Window W = parse(w);
   const int nl = (int)W.ln.size(), nr = (int)W.rn.size();
   DMRG_REQUIRE(n_left_ops >= 0 && n_right_ops >= 0 && (n_left_ops == 0 || left_ops) &&
@@ -173,16 +320,13 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
                  "su2: pair rank must be >= 0 and parity 0 or 1");
   }
   auto plan = std::make_unique<Su2Plan>();
+  plan->precision = precision;
   plan->psi_size = W.size;
   plan->psi.alloc((size_t)std::max<int64_t>(W.size, 1) * sizeof(double));
 
   // The stage-2 products: for each pair, each ket block (a, b) of psi, each
   // block A[a', a] of its left operator and B[b', b] of its right operator
   // with (a', b') a coupled block and a non-zero recoupling factor.
-  struct Prod {
-    int p, i, j;  // pair, block of B, block of A
-    double scale;
-  };
   std::vector<std::vector<Prod>> prods_of_r(n_right_ops);  // grouped by right operator
   std::map<std::tuple<int, int, int, int, int>, double> wcache;
   std::vector<std::vector<std::vector<int>>> lin(n_left_ops), rin(n_right_ops);
@@ -214,20 +358,19 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
   // row rowoff(a, b); stage 1 then multiplies every needed row of a right
   // sector by a block of B in one product.
   std::vector<int64_t> boff(nr + 1, 0), rowoff((size_t)nl * nr, -1), mb(nr, 0);
+  // (each block's rows start at a multiple of 8, the rows between are zero:
+  // the split-BF16 products read k-ranges of 16-byte aligned rows)
   for (int b = 0; b < nr; ++b) {
     for (int a = 0; a < nl; ++a)
       if (W.at(a, b) >= 0) {
         rowoff[(size_t)a * nr + b] = mb[b];
-        mb[b] += W.ld[a];
+        mb[b] += pad8(W.ld[a]);
       }
     boff[b + 1] = boff[b] + mb[b] * W.rd[b];
   }
   // Stage-1 products per right operator: block i of B -> the row range of
   // psi_b it multiplies (from the first to the last needed left sector) and
   // the workspace offset of T(r, i) (M_b x d_b').
-  struct S1 {
-    int64_t lo = -1, hi = -1, off = 0;
-  };
   std::vector<std::map<int, S1>> need(n_right_ops);
   std::vector<int64_t> rsize(n_right_ops, 0);
   for (int r = 0; r < n_right_ops; ++r) {
@@ -257,11 +400,13 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
     }
     if (acc > 0) chunks.push_back({r0, n_right_ops});
   }
-  plan->ws.alloc((size_t)std::max<int64_t>(plan->ws_doubles, 1) * sizeof(double));
+  const bool f64 = precision == DMRG_FP64;
+  if (f64) plan->ws.alloc((size_t)std::max<int64_t>(plan->ws_doubles, 1) * sizeof(double));
   double* T = plan->ws.as<double>();
-  plan->psi_b.alloc((size_t)std::max<int64_t>(W.size, 1) * sizeof(double));
+  plan->psi_b.alloc((size_t)std::max<int64_t>(boff[nr], 1) * sizeof(double));
   const double* P = plan->psi.as<double>();
   double* Pb = plan->psi_b.as<double>();
+  launch_fill(Pb, 0.0, boff[nr], s);  // the rows between blocks stay zero
   {
     std::vector<CopyTask> tasks;
     for (int a = 0; a < nl; ++a)
@@ -282,8 +427,10 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
     int64_t off = 0;
     for (int r = chunks[c].first; r < chunks[c].second; ++r)
       for (auto& kv : need[r]) {
+        const int b = right_ops[r].in_sector[kv.first], b2 = right_ops[r].out_sector[kv.first];
         kv.second.off = off;
-        off += mb[right_ops[r].in_sector[kv.first]] * W.rd[right_ops[r].out_sector[kv.first]];
+        off += mb[b] * W.rd[b2];
+        plan->flops1 += 2.0 * (kv.second.hi - kv.second.lo) * W.rd[b] * W.rd[b2];
       }
     size_t nseg = 0;
     for (int r = chunks[c].first; r < chunks[c].second; ++r)
@@ -291,8 +438,13 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
         const dmrg_su2_operator& A = left_ops[pairs[x.p].left_op];
         const dmrg_su2_operator& B = right_ops[r];
         const int a2 = A.out_sector[x.j], a = A.in_sector[x.j], b2 = B.out_sector[x.i], b = B.in_sector[x.i];
-        const int64_t to = need[r].at(x.i).off + rowoff[(size_t)a * nr + b] * W.rd[b2];
-        outs[c][{a2, b2}].push_back({A.data + A.offset[x.j], T + to, W.ld[a], W.rd[b2], W.ld[a], 0, x.scale});
+        auto& list = outs[c][{a2, b2}];
+        if (f64) {
+          const int64_t to = need[r].at(x.i).off + rowoff[(size_t)a * nr + b] * W.rd[b2];
+          list.push_back({A.data + A.offset[x.j], T + to, W.ld[a], W.rd[b2], W.ld[a], 0, x.scale});
+        } else {
+          list.emplace_back();  // counted only: the BF16 lists are built from the products
+        }
         plan->flops2 += 2.0 * W.ld[a2] * W.ld[a] * W.rd[b2];
         ++nseg;
       }
@@ -319,6 +471,11 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
   }
   double* Part = plan->part.as<double>();
   const auto tiles = su2_tiles();
+  if (precision == DMRG_BF16X3) {
+    outs.clear();
+    build_bf16(*plan, W, left_ops, right_ops, prods_of_r, pairs, need, chunks, mb, boff, rowoff, seg_per_part, s);
+    return plan;
+  }
   for (size_t c = 0; c < chunks.size(); ++c) {
     // stage 1: rows [lo, hi) of T(r, i) = psi_b B_r[i]^T (M_b x d_b'),
     // psi_b holding the blocks (a, b) stacked by a
@@ -335,7 +492,6 @@ std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, cons
         b1.segs.push_back({Pb + boff[b] + e.lo * W.rd[b], B.data + B.offset[i], W.rd[b], W.rd[b], W.rd[b],
                            kTransB, 1.0});
         b1.add_problem(T + e.off + e.lo * W.rd[b2], W.rd[b2], (int)(e.hi - e.lo), W.rd[b2], s0, s0 + 1, 0);
-        plan->flops1 += 2.0 * (e.hi - e.lo) * W.rd[b] * W.rd[b2];
       }
     }
     // stage 2: each output's products in contiguous pieces, one per partial sum
@@ -373,9 +529,17 @@ void su2_run(Su2Plan& p, const double* psi, double* sigma, hipStream_t s) {
   DMRG_HIP(hipMemcpyAsync(P, psi, (size_t)p.psi_size * sizeof(double), hipMemcpyDeviceToDevice, s));
   launch_copy_tasks(p.regroup.as<CopyTask>(), p.n_regroup, false, s);
   launch_fill(p.part.as<double>(), 0.0, (int64_t)p.n_parts * p.psi_size, s);
-  for (size_t c = 0; c < p.s1.size(); ++c) {
-    launch_gemm_f64(p.s1[c], s, 1);
-    launch_gemm_f64(p.s2[c], s, 2);
+  if (p.precision == DMRG_BF16X3) {
+    launch_pack_bf16(p.psi_pack_ops.as<PackOp>(), p.n_psi_pack, p.psi_pack_chunks, p.psi_pack.as<uint16_t>(), s);
+    for (size_t c = 0; c < p.s1b.size(); ++c) {
+      launch_gemm_bf16(p.s1b[c], true, kOutBf16, 1, s);
+      launch_gemm_bf16(p.s2b[c], true, kOutF64, 2, s);
+    }
+  } else {
+    for (size_t c = 0; c < p.s1.size(); ++c) {
+      launch_gemm_f64(p.s1[c], s, 1);
+      launch_gemm_f64(p.s2[c], s, 2);
+    }
   }
   launch_lincomb(sigma, p.part.as<double>(), p.psi_size, p.n_parts, p.ones.as<double>(), p.psi_size, 0.0, s);
 }

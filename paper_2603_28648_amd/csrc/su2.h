@@ -10,6 +10,7 @@
 #include "common.h"
 #include "dmrg.h"
 #include "gemm.h"
+#include "gemm_bf16.h"
 
 namespace dmrg {
 
@@ -29,6 +30,14 @@ struct Su2Plan {
   DevBuf part, ones;  // n_parts partial sums of sigma (psi_size each), and n_parts ones
   int n_parts = 1;
   std::vector<DevGemm> s1, s2;
+  // split-BF16x3 plans: packed operator blocks, psi_b packed per call, the
+  // BF16 hi/lo workspace and the descriptors
+  int precision = DMRG_FP64;
+  DevBuf opk, psi_pack, psi_pack_ops, wsk;
+  int n_psi_pack = 0;
+  int64_t psi_pack_chunks = 0;
+  std::vector<int64_t> psi_poff;
+  std::vector<DevGemmB> s1b, s2b;
   int64_t n_segments = 0, ws_doubles = 0;
   double flops1 = 0, flops2 = 0;
 };
@@ -40,10 +49,11 @@ constexpr size_t kSu2PartsPerLaunch = 8192;
 constexpr int kSu2MaxParts = 256;
 constexpr int64_t kSu2PartialBudget = (int64_t)1 << 27;
 
-// Builds the plan (host checks as dmrg_su2_sigma; ws_budget in doubles).
+// Builds the plan (host checks as dmrg_su2_sigma; precision DMRG_FP64 or
+// DMRG_BF16X3; ws_budget in doubles).
 std::unique_ptr<Su2Plan> su2_plan(const dmrg_su2_window& w, int n_left_ops, const dmrg_su2_operator* left_ops,
                                   int n_right_ops, const dmrg_su2_operator* right_ops, int n_pairs,
-                                  const dmrg_su2_pair* pairs, int64_t ws_budget, hipStream_t s);
+                                  const dmrg_su2_pair* pairs, int precision, int64_t ws_budget, hipStream_t s);
 
 // sigma = the plan's contraction of psi, stream-ordered (no synchronisation).
 void su2_run(Su2Plan& p, const double* psi, double* sigma, hipStream_t s);

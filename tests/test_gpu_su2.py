@@ -17,6 +17,10 @@ from synthetic.su2 import sector_window, random_operator, pack, unpack, cas89_10
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
+# split-BF16x3: operands and the stage-1 intermediate as BF16 hi + lo carry
+# a relative error of about 2^-18 (3.8e-6) per element, products accumulate
+# in FP32 and are flushed into FP64 per product; measured 6.3e-6
+TOL_X3 = 2e-5
 INVALID_ARG = -1  # DMRG_ERR_INVALID_ARG
 
 
@@ -117,6 +121,27 @@ def test_su2_plan_applied_twice_and_in_place(ctx):
         assert close(buf.cpu().numpy(), oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs, x))
 
 
+@pytest.mark.parametrize("n,tS,dmax,seed", CASES)
+def test_su2_bf16x3_plan_matches_the_oracle(ctx, n, tS, dmax, seed):
+    """The split-BF16x3 plan against the oracle: relative error of the whole
+    vector below TOL_X3, and no element off by more than TOL_X3 max|sigma|."""
+    import torch
+    print(f"su2 bf16x3 sigma: n={n} 2S={tS} dmax={dmax} seed={seed}", flush=True)
+    lsec, rsec, lops, rops, pairs, size, rng = case_ops(n, tS, dmax, seed)
+    psi = rng.normal(size=size)
+    ref = oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs, psi)
+    L, R = device_ops(lops), device_ops(rops)
+    with ctx.su2_plan(lsec, rsec, n, tS, L, R, pairs, precision="bf16x3") as plan:
+        out = torch.full((size,), float("nan"), dtype=torch.float64, device="cuda")
+        plan.sigma(dev(psi), out)
+        torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"  relative error {rel:.2e}", flush=True)
+    assert rel <= TOL_X3 and rel > 0
+    assert np.abs(got - ref).max() <= TOL_X3 * np.abs(ref).max()
+
+
 def test_su2_plan_in_workspace_chunks():
     """A context with a 1 MiB stage-1 budget splits the right operators
     into several chunks; the result is the oracle's."""
@@ -137,16 +162,22 @@ def test_su2_plan_in_workspace_chunks():
         lsec, rsec, lops, rops, pairs, size, rng = case_ops(n, tS, 260, 4)
         psi = rng.normal(size=size)
         L, R = device_ops(lops), device_ops(rops)
-        with c.su2_plan(lsec, rsec, n, tS, L, R, pairs) as plan:
-            info = plan.info()
-            print(f"su2 chunks: {info}", flush=True)
-            # a chunk holds at least one right operator, so one whose products
-            # exceed the budget gets a chunk of its own
-            assert info["n_chunks"] > 1
-            out = torch.empty(size, dtype=torch.float64, device="cuda")
-            plan.sigma(dev(psi), out)
-            torch.cuda.synchronize()
-        assert close(out.cpu().numpy(), oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs, psi))
+        ref = oracle_sigma(lsec, rsec, n, tS, lops, rops, pairs, psi)
+        for precision in ("fp64", "bf16x3"):
+            with c.su2_plan(lsec, rsec, n, tS, L, R, pairs, precision=precision) as plan:
+                info = plan.info()
+                print(f"su2 chunks ({precision}): {info}", flush=True)
+                # a chunk holds at least one right operator, so one whose products
+                # exceed the budget gets a chunk of its own
+                assert info["n_chunks"] > 1
+                out = torch.empty(size, dtype=torch.float64, device="cuda")
+                plan.sigma(dev(psi), out)
+                torch.cuda.synchronize()
+            got = out.cpu().numpy()
+            if precision == "fp64":
+                assert close(got, ref)
+            else:
+                assert np.linalg.norm(got - ref) <= TOL_X3 * np.linalg.norm(ref)
     finally:
         c.close()
 
@@ -188,7 +219,15 @@ def test_su2_sigma_cas89_102_sampled(ctx):
         out = torch.full_like(w["psi"], float("nan"))
         plan.sigma(w["psi"], out)
         torch.cuda.synchronize()
+    with ctx.su2_plan(lsec, rsec, n, tS, w["left_ops"], w["right_ops"], w["pairs"], precision="bf16x3") as plan:
+        out3 = torch.full_like(w["psi"], float("nan"))
+        plan.sigma(w["psi"], out3)
+        torch.cuda.synchronize()
+    rel3 = float(torch.linalg.norm(out3 - out) / torch.linalg.norm(out))
+    print(f"su2 CAS(89,102) bf16x3 against FP64: relative error {rel3:.2e}", flush=True)
+    assert rel3 <= TOL_X3
     got = unpack(lsec, rsec, n, tS, out.cpu().numpy())
+    got3 = unpack(lsec, rsec, n, tS, out3.cpu().numpy())
     psi = unpack(lsec, rsec, n, tS, w["psi"].cpu().numpy())
     blocks = su2.coupled_blocks(lsec, rsec, n, tS)
     sizes = [lsec[a][2] * rsec[b][2] for a, b in blocks]
@@ -223,6 +262,7 @@ def test_su2_sigma_cas89_102_sampled(ctx):
         print(f"su2 CAS(89,102) block {k}: max|ref| {np.abs(ref[k]).max():.3e}", flush=True)
         assert np.abs(ref[k]).max() > 1.0
         assert np.abs(got[k] - ref[k]).max() <= TOL * np.abs(ref[k]).max()
+        assert np.abs(got3[k] - ref[k]).max() <= TOL_X3 * np.abs(ref[k]).max()
 
 
 def test_su2_operator_past_its_tensor_is_refused(ctx):
