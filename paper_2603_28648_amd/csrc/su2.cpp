@@ -15,7 +15,8 @@
 // each output block (NN products).  A plan keeps both stages' descriptors per
 // chunk of right operators, whose stage-1 products fit the workspace budget;
 // stage 1 only forms the rows some pair's stage 2 reads, and long stage-2
-// product lists are split over partial sums of sigma.
+// product lists are split over partial sums of sigma.  Split-BF16x3 plans
+// run the same products on the BF16 kernel from packed hi/lo copies.
 #include "su2.h"
 
 #include <cmath>
