@@ -32,3 +32,26 @@ def test_psi_size_of_a_window_without_coupled_blocks_is_zero():
 def test_invalid_window_is_an_error(lsec, rsec, n, tS):
     with pytest.raises(DMRGError):
         su2_psi_size(lsec, rsec, n, tS)
+
+
+def test_cas89_102_window_shape():
+    """The spin-adapted workload's sectors: 2048 multiplets on each side,
+    N and 2S of equal parity, and the packed vector the library sizes as
+    the oracle's coupled blocks."""
+    from synthetic.su2 import cas89_102_window, hamiltonian_pair_types, operator_layout
+    lsec, rsec, n, tS = cas89_102_window(np.random.default_rng(102))
+    assert (n, tS) == (89, 5)
+    for secs in (lsec, rsec):
+        assert sum(d for _, _, d in secs) == 2048
+        assert all(N >= 0 and ts >= 0 and (N - ts) % 2 == 0 and d >= 1 for N, ts, d in secs)
+        assert len(set((N, ts) for N, ts, _ in secs)) == len(secs)
+    want = sum(lsec[a][2] * rsec[b][2] for a, b in su2.coupled_blocks(lsec, rsec, n, tS))
+    assert su2_psi_size(lsec, rsec, n, tS) == want
+    types = hamiltonian_pair_types(51, 51)
+    assert sum(t[0] for t in types) == 2 + 4 * 51 + 2 * (1326 + 1275) + 2 * 2601
+    for count, dnl, tk, dnr, parity in types:
+        assert dnl + dnr == 0 and parity == abs(dnl) % 2  # particle number kept; fermion parity of the right side
+        blocks, size = operator_layout(lsec, dnl, tk)
+        assert blocks and size == sum(lsec[o][2] * lsec[i][2] for o, i, _ in blocks)
+        for o, i, _ in blocks:  # particle change and the rank's triangle condition
+            assert lsec[o][0] == lsec[i][0] + dnl and abs(lsec[o][1] - lsec[i][1]) <= tk <= lsec[o][1] + lsec[i][1]
