@@ -140,6 +140,34 @@ std::pair<std::pair<int, int>, std::pair<int, int>> su2_tiles() {
   return {t[0], t[1]};
 }
 
+// BF16 tile shapes of the split-BF16x3 stages: 64 x 128 for stage 1 (its
+// BF16 hi/lo output), 64 x 64 for stage 2 (FP64 flush with each product's
+// scale), measured at the CAS(89,102)-shaped workload (ms per sigma): 85.6,
+// against 117.9 with 128 x 128 and 90.0 with 128 x 64 for stage 1, 89.6
+// with 128 x 64 and 86.2 with 64 x 128 for stage 2.
+// DMRG_SU2_BF16_SHAPE="s1,s2" overrides, each 64x64, 128x64 or 64x128
+// (stage 1 also 128x128).
+std::pair<int, int> su2_bf16_shapes() {
+  int sh[2] = {kShape64x128, kShape64x64};
+  if (const char* e = std::getenv("DMRG_SU2_BF16_SHAPE")) {
+    auto parse = [](const std::string& w, int& o, bool square) {
+      if (w == "64x64") o = kShape64x64;
+      else if (w == "128x64") o = kShape128x64;
+      else if (w == "64x128") o = kShape64x128;
+      else if (square && w == "128x128") o = kShape128x128s3;
+      else return false;
+      return true;
+    };
+    const std::string v(e);
+    const size_t comma = v.find(',');
+    DMRG_REQUIRE(comma != std::string::npos && parse(v.substr(0, comma), sh[0], true) &&
+                     parse(v.substr(comma + 1), sh[1], false),
+                 kErrInvalidArg, "DMRG_SU2_BF16_SHAPE must be \"s1,s2\", each 64x64, 128x64 or 64x128 "
+                 "(stage 1 also 128x128)");
+  }
+  return {sh[0], sh[1]};
+}
+
 }  // namespace
 
 double wigner_6j(int tj1, int tj2, int tj3, int tj4, int tj5, int tj6) {
@@ -194,7 +222,6 @@ void build_bf16(Su2Plan& plan, const Window& W, const dmrg_su2_operator* left_op
       if (!lpos.count({l, x.j}))
         lpos[{l, x.j}] = add(A.data + A.offset[x.j], W.ld[A.out_sector[x.j]], W.ld[A.in_sector[x.j]]);
     }
-  const int64_t lsize = total;
   for (int r = 0; r < (int)need.size(); ++r)
     for (auto& kv : need[r]) {
       const dmrg_su2_operator& B = right_ops[r];
@@ -210,12 +237,11 @@ void build_bf16(Su2Plan& plan, const Window& W, const dmrg_su2_operator* left_op
     }
     DMRG_HIP(hipStreamSynchronize(s));
   }
-  (void)lsize;
   // psi_b packed per call: one pass over every right sector's M_b x d_b matrix
+  std::vector<int64_t> poff(nr, 0);
   {
     std::vector<PackOp> pops;
     int64_t c8 = 0, at = 0;
-    std::vector<int64_t> poff(nr, 0);
     for (int b = 0; b < nr; ++b) {
       if (mb[b] == 0) continue;
       const int kp = (int)pad8(W.rd[b]);
@@ -230,9 +256,9 @@ void build_bf16(Su2Plan& plan, const Window& W, const dmrg_su2_operator* left_op
       DMRG_HIP(hipMemcpy(plan.psi_pack_ops.p, pops.data(), pops.size() * sizeof(PackOp), hipMemcpyHostToDevice));
     plan.n_psi_pack = (int)pops.size();
     plan.psi_pack_chunks = c8;
-    plan.psi_poff = poff;
   }
   const uint16_t* Q = plan.psi_pack.as<uint16_t>();
+  const auto shapes = su2_bf16_shapes();
   plan.wsk.alloc((size_t)std::max<int64_t>(2 * plan.ws_doubles, 8) * sizeof(uint16_t));
   uint16_t* T = plan.wsk.as<uint16_t>();
   const int64_t tlo = plan.ws_doubles;  // lo plane of the workspace
@@ -241,7 +267,7 @@ void build_bf16(Su2Plan& plan, const Window& W, const dmrg_su2_operator* left_op
   for (size_t c = 0; c < chunks.size(); ++c) {
     // stage 1: columns [lo, pad8(hi)) of T(r, i)^T = B_r[i] psi_b^T (d_b' x M_b)
     GemmBatchB b1;
-    b1.shape = kShape64x128;
+    b1.shape = shapes.first;
     for (int r = chunks[c].first; r < chunks[c].second; ++r) {
       const dmrg_su2_operator& B = right_ops[r];
       for (auto& kv : need.at(r)) {
@@ -250,7 +276,7 @@ void build_bf16(Su2Plan& plan, const Window& W, const dmrg_su2_operator* left_op
         const int b2 = B.out_sector[i], b = B.in_sector[i];
         const int64_t kp = pad8(W.rd[b]);
         const size_t s0 = b1.segs.size();
-        b1.segs.push_back({K + rpos.at({r, i}), Q + plan.psi_poff[b] + e.lo * kp, (int64_t)W.rd[b2] * kp,
+        b1.segs.push_back({K + rpos.at({r, i}), Q + poff[b] + e.lo * kp, (int64_t)W.rd[b2] * kp,
                            mb[b] * kp, (int)kp, (int)kp, W.rd[b], kTransB, 1.0});
         b1.add_problem(T + e.off + e.lo, tlo, (int)mb[b], W.rd[b2], (int)(pad8(e.hi) - e.lo), s0, s0 + 1, 0);
       }
@@ -269,7 +295,7 @@ void build_bf16(Su2Plan& plan, const Window& W, const dmrg_su2_operator* left_op
                                   (int64_t)W.ld[a2] * kp, tlo, (int)kp, (int)mb[b], W.ld[a], kTransB, x.scale});
       }
     GemmBatchB b2;
-    b2.shape = kShape64x64;
+    b2.shape = shapes.second;
     for (auto& kv : outs) {
       const int a2 = kv.first.first, bb2 = kv.first.second;
       const std::vector<GemmSegB>& g = kv.second;

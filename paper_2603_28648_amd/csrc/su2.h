@@ -36,7 +36,6 @@ struct Su2Plan {
   DevBuf opk, psi_pack, psi_pack_ops, wsk;
   int n_psi_pack = 0;
   int64_t psi_pack_chunks = 0;
-  std::vector<int64_t> psi_poff;
   std::vector<DevGemmB> s1b, s2b;
   int64_t n_segments = 0, ws_doubles = 0;
   double flops1 = 0, flops2 = 0;
