@@ -34,6 +34,12 @@ holds the plain definitions that a spin-adapted sigma has to reproduce:
   (enlarged-block) tensor operators of rank 0, 1/2 and 1, each a product of
   reduced block matrices weighted by this coefficient, which is what the
   grouped block GEMMs would execute.
+* wigner_9j and product_coupling / product_operator: the reduced blocks of
+  a coupled product [A^k1 x B^k2]^k of operators on two subsystems (a block
+  operator times a site operator: the renormalisation step that builds the
+  enlarged block's tensor operators), weighted by
+      sqrt((2S + 1)(2k + 1)(2S_a' + 1)(2S_b' + 1)) {S_a' S_a k1; S_b' S_b k2; S' S k}
+  and the fermion sign (-1)^(p(B) N_a).
 
 Pins (tests/test_oracle_su2.py): Clebsch-Gordan orthonormality, the closed
 form for j2 = 1/2 and the eigenvectors of J^2 built from explicit spin
@@ -43,7 +49,13 @@ it; multiplet bases against S^2, S_+ and the sector dimensions; heff_su2 at
 complete bases against the full-CI eigenvalues of spin S (states of the
 (N, 2S_z = 2S) sector with <S^2> = S(S+1), from oracle.fock), and at two
 values of M; the scalar-product rule (with fermion signs) against the
-operator built component by component on the Fock space.
+operator built component by component on the Fock space; the 9j symbol
+against its reduction to a 6j symbol when one entry is zero and against the
+orthogonality of the recoupling matrix it defines; product_operator against
+the coupled product built component by component on the Fock space, for
+ranks 0, 1/2, 1 and 3/2 and particle changes 0, +-1, 2 (a dropped (2S + 1)
+factor and a bra/ket exchange in the 9j symbol each fail it), and at k = 0
+against scalar_coupling.
 """
 from math import factorial, sqrt
 
@@ -113,6 +125,59 @@ def scalar_coupling(tSa2, tSb2, tSa, tSb, tS, tk):
     docstring; primed spins first)."""
     ph = (tSa + tSb2 + tS + tk) // 2
     return (-1) ** ph * sqrt((tSa2 + 1) * (tSb2 + 1) / (tk + 1)) * wigner_6j(tSa, tSb, tS, tSb2, tSa2, tk)
+
+
+def wigner_9j(tj1, tj2, tj3, tj4, tj5, tj6, tj7, tj8, tj9):
+    """{j1 j2 j3; j4 j5 j6; j7 j8 j9} (arguments doubled) as the sum over x of
+    (-1)^(2x) (2x + 1) {j1 j4 j7; j8 j9 x} {j2 j5 j8; j4 x j6} {j3 j6 j9; x j1 j2},
+    the standard reduction of a 9j symbol to 6j symbols over the common
+    index x (its range: the triangles (j1, j9, x), (j8, j4, x), (j2, j6, x))."""
+    lo = max(abs(tj1 - tj9), abs(tj4 - tj8), abs(tj2 - tj6))
+    hi = min(tj1 + tj9, tj4 + tj8, tj2 + tj6)
+    s = 0.0
+    for tx in range(lo, hi + 1, 2):
+        s += ((-1) ** tx * (tx + 1) * wigner_6j(tj1, tj4, tj7, tj8, tj9, tx)
+              * wigner_6j(tj2, tj5, tj8, tj4, tx, tj6) * wigner_6j(tj3, tj6, tj9, tx, tj1, tj2))
+    return s
+
+
+def product_coupling(tSa2, tSb2, tS2, tSa, tSb, tS, tk1, tk2, tk):
+    """<(a' S_a', b' S_b') S' || [A^k1 x B^k2]^k || (a S_a, b S_b) S> for unit
+    reduced elements of A (first subsystem) and B (second), in the
+    Clebsch-Gordan convention of the reduced elements and without the
+    fermion sign:
+        sqrt((2S + 1)(2k + 1)(2S_a' + 1)(2S_b' + 1)) {S_a' S_a k1; S_b' S_b k2; S' S k}.
+    (The tensor-product theorem for operators on two subsystems, restated
+    from the 3j convention <j'||T||j>_3j = sqrt(2j' + 1) <j'||T||j>_CG; the
+    phases (-1)^(2k) of that conversion cancel since k1 + k2 + k is an
+    integer.  With k = 0 it is scalar_coupling.)"""
+    return (sqrt((tS + 1) * (tk + 1) * (tSa2 + 1) * (tSb2 + 1))
+            * wigner_9j(tSa2, tSa, tk1, tSb2, tSb, tk2, tS2, tS, tk))
+
+
+def product_operator(sec1, sec2, t1, t2, tk1, tk2, tk, parity2):
+    """Reduced blocks of [A^k1 x B^k2]^k on the coupled multiplets of two
+    subsystems (the renormalisation of a block operator times a site
+    operator).  sec1, sec2: the sectors (N, 2S, d) of the subsystems; t1, t2:
+    reduced blocks {(out, in): matrix} of A and B; parity2: fermion parity of
+    B (it passes the ket's N_1 electrons of the first subsystem).  A coupled
+    sector is (i1, i2, 2S) with multiplets (alpha1, alpha2), alpha1 slowest;
+    returns {((i1', i2', 2S'), (i1, i2, 2S)): matrix}."""
+    out = {}
+    for (i1p, i1), a in t1.items():
+        for (i2p, i2), b in t2.items():
+            n1, ts1 = sec1[i1][0], sec1[i1][1]
+            ts2 = sec2[i2][1]
+            tsa2, tsb2 = sec1[i1p][1], sec2[i2p][1]
+            sign = -1.0 if (parity2 and n1 % 2) else 1.0
+            for tS in range(abs(ts1 - ts2), ts1 + ts2 + 1, 2):
+                for tS2 in range(abs(tsa2 - tsb2), tsa2 + tsb2 + 1, 2):
+                    c = product_coupling(tsa2, tsb2, tS2, ts1, ts2, tS, tk1, tk2, tk)
+                    if c == 0.0:
+                        continue
+                    key = ((i1p, i2p, tS2), (i1, i2, tS))
+                    out[key] = out.get(key, 0.0) + sign * c * np.kron(a, b)
+    return out
 
 
 # ---- multiplet bases of a block of orbitals ----------------------------------

@@ -294,3 +294,90 @@ def test_contract_scalar_products_against_the_fock_space_operators():
     got_flat = np.array([got[(ia, ib)][al, be] for (ia, al, ib, be) in basis])
     assert np.abs(ref).max() > 1e-2
     assert np.allclose(got_flat, ref, atol=1e-11)
+
+
+@pytest.mark.parametrize("spins", [(1, 1, 2, 1, 1, 2), (2, 1, 1, 1, 2, 3), (3, 2, 1, 1, 2, 2), (2, 2, 2, 2, 2, 4)])
+def test_9j_with_a_zero_entry_is_a_6j(spins):
+    """{a b e; c d e; f f 0} = (-1)^(b + c + e + f) {a b e; d c f} / sqrt((2e + 1)(2f + 1))."""
+    a, b, e, c, d, f = spins
+    got = su2.wigner_9j(a, b, e, c, d, e, f, f, 0)
+    want = (-1) ** ((b + c + e + f) // 2) * su2.wigner_6j(a, b, e, d, c, f) / sqrt((e + 1) * (f + 1))
+    assert abs(got - want) < 1e-13
+
+
+@pytest.mark.parametrize("j1,j2,j3,j4,J", [(1, 1, 1, 1, 2), (2, 1, 1, 2, 2), (1, 2, 3, 1, 3), (2, 2, 2, 2, 4)])
+def test_9j_recoupling_matrix_is_orthogonal(j1, j2, j3, j4, J):
+    """The transformation between the couplings ((j1 j2) j12, (j3 j4) j34) J
+    and ((j1 j3) j13, (j2 j4) j24) J, sqrt((2j12+1)(2j34+1)(2j13+1)(2j24+1))
+    times the 9j symbol, is an orthogonal matrix (and square)."""
+    def pairs(ja, jb, jc, jd):
+        return [(x, y) for x in range(abs(ja - jb), ja + jb + 1, 2) for y in range(abs(jc - jd), jc + jd + 1, 2)
+                if su2._triangle(x, y, J)]
+    rows, cols = pairs(j1, j2, j3, j4), pairs(j1, j3, j2, j4)
+    M = np.array([[sqrt((x + 1) * (y + 1) * (u + 1) * (v + 1)) * su2.wigner_9j(j1, j2, x, j3, j4, y, u, v, J)
+                   for (u, v) in cols] for (x, y) in rows])
+    assert M.shape[0] == M.shape[1] > 1
+    assert np.allclose(M.T @ M, np.eye(len(cols)), atol=1e-12)
+
+
+def test_product_coupling_of_rank_zero_is_the_scalar_rule():
+    for tsa2, tsb2, tsa, tsb, ts, tk in [(1, 1, 1, 1, 0, 2), (2, 1, 0, 1, 1, 2), (1, 2, 1, 0, 1, 1), (2, 2, 2, 2, 2, 2)]:
+        got = su2.product_coupling(tsa2, tsb2, ts, tsa, tsb, ts, tk, tk, 0)
+        assert abs(got - su2.scalar_coupling(tsa2, tsb2, tsa, tsb, ts, tk)) < 1e-13
+
+
+@pytest.mark.parametrize("dn1,tk1,dn2,tk2,tk", [(0, 0, 1, 1, 1), (1, 1, 1, 1, 0), (1, 1, 1, 1, 2), (1, 1, -1, 1, 2),
+                                                (0, 2, 0, 2, 2), (2, 0, -1, 1, 1), (-1, 1, 0, 2, 3)])
+def test_product_operator_against_the_fock_space(dn1, tk1, dn2, tk2, tk):
+    """[A^k1 x B^k2]^k of a two-orbital block operator A and a one-orbital
+    site operator B (the renormalisation step of spin-adapted DMRG), built
+    component by component on the Fock space with the Jordan-Wigner sign of
+    B passing the block's electrons, against product_operator on the coupled
+    multiplets of block x site."""
+    nl, nr = 2, 1
+    rng = np.random.default_rng(40 + 7 * dn1 + 3 * tk1 + tk)
+    left, right = su2.multiplets(nl), su2.multiplets(nr)
+    sec1 = [(M.n, M.tS, M.dim) for M in left]
+    sec2 = [(M.n, M.tS, M.dim) for M in right]
+    t1, A = block_tensor(left, nl, dn1, tk1, rng)
+    t2, B = block_tensor(right, nr, dn2, tk2, rng)
+    full_l = DetSpace.full(nl)
+    nL = np.bitwise_count(full_l.dets.astype(np.uint64)).astype(int)
+    p2 = abs(dn2) % 2
+    sign = np.diag((-1.0) ** (p2 * nL))
+    X = {}
+    for tq in range(-tk, tk + 1, 2):
+        X[tq] = sum(su2.clebsch_gordan(tk1, q1, tk2, tq - q1, tk, tq) * np.kron(B[tq - q1], A[q1] @ sign)
+                    for q1 in range(-tk1, tk1 + 1, 2) if abs(tq - q1) <= tk2)
+    rule = su2.product_operator(sec1, sec2, t1, t2, tk1, tk2, tk, p2)
+    checked = 0
+    for n in range(0, 2 * (nl + nr) + 1):
+        n2 = n + dn1 + dn2
+        if not 0 <= n2 <= 2 * (nl + nr):
+            continue
+        for tJ in range(n % 2, 2 * (nl + nr) + 1, 2):
+            kb = su2.coupled_basis(left, right, n, tJ)
+            if not kb:
+                continue
+            for tJ2 in range(n2 % 2, 2 * (nl + nr) + 1, 2):
+                bb = su2.coupled_basis(left, right, n2, tJ2)
+                if not bb or not su2._triangle(tJ, tk, tJ2):
+                    continue
+                tM = tJ
+                Pk, sk = su2.coupled_vectors(left, right, nl, nr, n, tJ, tM, kb)
+                for tq in range(-tk, tk + 1, 2):
+                    tM2 = tM + tq
+                    cg = su2.clebsch_gordan(tJ, tM, tk, tq, tJ2, tM2) if abs(tM2) <= tJ2 else 0.0
+                    if abs(cg) < 1e-12:
+                        continue
+                    Pb, sb = su2.coupled_vectors(left, right, nl, nr, n2, tJ2, tM2, bb)
+                    brute = Pb.T @ X[tq][np.ix_(np.asarray(sb.dets), np.asarray(sk.dets))] @ Pk / cg
+                    want = np.zeros_like(brute)
+                    for c2, (ia2, al2, ib2, be2) in enumerate(bb):
+                        for c, (ia, al, ib, be) in enumerate(kb):
+                            blk = rule.get(((ia2, ib2, tJ2), (ia, ib, tJ)))
+                            if blk is not None:
+                                want[c2, c] = blk[al2 * sec2[ib2][2] + be2, al * sec2[ib][2] + be]
+                    assert np.allclose(brute, want, atol=1e-11)
+                    checked += int(np.abs(brute).max() > 1e-3)
+    assert checked >= 3
