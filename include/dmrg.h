@@ -457,6 +457,38 @@ dmrg_status dmrg_su2_plan_info(dmrg_ctx ctx, dmrg_su2_plan plan, dmrg_su2_info* 
  * a no-op. */
 dmrg_status dmrg_su2_plan_destroy(dmrg_ctx ctx, dmrg_su2_plan plan);
 
+/* The renormalisation step of spin-adapted operators (Numerical procedure
+ * section): the reduced blocks of the coupled product X^k = [A^k1 x B^k2]^k
+ * of an operator A on subsystem 1 (a block) and B on subsystem 2 (a site,
+ * or any second block),
+ *   <(a' S_a', b' S_b') S' || X^k || (a S_a, b S_b) S>
+ *     = (-1)^(p(B) N_a) sqrt((2S + 1)(2k + 1)(2S_a' + 1)(2S_b' + 1))
+ *       {S_a' S_a k1; S_b' S_b k2; S' S k} <a'||A||a> <b'||B||b>
+ * (a Wigner 9j symbol; reduced elements in the Clebsch-Gordan convention of
+ * dmrg_su2_sigma).  The coupled sectors of the two subsystems are (i1, i2,
+ * 2S) for every sector i1 of subsystem 1, i2 of subsystem 2 and S in
+ * S_i1 x S_i2, numbered in that order (i1 slowest, then i2, then 2S
+ * ascending); a coupled sector holds d_i1 d_i2 multiplets, (alpha1, alpha2)
+ * with alpha1 slowest.  sectors: the left arrays of the window describe
+ * subsystem 1, the right arrays subsystem 2 (n_elec and two_s are not
+ * used).  An output block is the Kronecker product of one block of A and
+ * one of B, scaled; blocks are ordered by A's block, then B's, then 2S,
+ * then 2S'; blocks whose coefficient vanishes are left out.
+ * dmrg_su2_product_size (host only; a and b need only their sector arrays)
+ * gives the number of output blocks and of output elements;
+ * dmrg_su2_product writes the blocks' sectors and element offsets (host
+ * arrays of n_blocks) and their data (device, n_elems, row-major blocks),
+ * synchronising the context stream.  Errors: DMRG_ERR_INVALID_ARG for an
+ * invalid sector list, a block sector out of range, negative ranks or a
+ * parity other than 0 or 1. */
+dmrg_status dmrg_su2_product_size(const dmrg_su2_window* sectors, const dmrg_su2_operator* a,
+                                  const dmrg_su2_operator* b, int32_t two_k1, int32_t two_k2,
+                                  int32_t two_k, int32_t* n_blocks, int64_t* n_elems);
+dmrg_status dmrg_su2_product(dmrg_ctx ctx, const dmrg_su2_window* sectors, const dmrg_su2_operator* a,
+                             const dmrg_su2_operator* b, int32_t two_k1, int32_t two_k2, int32_t two_k,
+                             int32_t parity_b, int32_t* out_sector, int32_t* in_sector, int64_t* offset,
+                             double* data);
+
 /* Diagnostic: copies diag(H_eff) of the current window (the Davidson
  * preconditioner; psi layout, device pointer, length dmrg_psi_size). */
 dmrg_status dmrg_debug_diag(dmrg_ctx ctx, double* out);

@@ -150,6 +150,15 @@ EXPORTS = {
     "dmrg_su2_plan_sigma": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "dmrg_su2_plan_info": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Su2Info)]),
     "dmrg_su2_plan_destroy": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p]),
+    "dmrg_su2_product_size": (ctypes.c_int32, [ctypes.POINTER(Su2Window), ctypes.POINTER(Su2Operator),
+                                               ctypes.POINTER(Su2Operator), ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_int64)]),
+    "dmrg_su2_product": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Su2Window), ctypes.POINTER(Su2Operator),
+                                          ctypes.POINTER(Su2Operator), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.c_void_p]),
     "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -614,6 +623,26 @@ class Context:
         for v in vecs:
             if v.numel() != n:
                 raise ValueError(f"expected {n} elements, got {v.numel()}")
+
+    def su2_product(self, sectors1, sectors2, a_op, b_op, tk1, tk2, tk, parity_b):
+        """dmrg_su2_product: the reduced blocks of [A^k1 x B^k2]^k (operators
+        as in _su2_args, A on the subsystem of sectors1, B on sectors2).
+        Returns (blocks [(out coupled sector, in coupled sector, offset)],
+        float64 CUDA tensor of the data)."""
+        import torch
+        keep = []
+        wptr, _, la, _, ra, _, _ = self._su2_args(sectors1, sectors2, 0, 0, [a_op], [b_op], [], keep)
+        nb, ne = ctypes.c_int32(), ctypes.c_int64()
+        self._check(self.lib.dmrg_su2_product_size(wptr, la, ra, int(tk1), int(tk2), int(tk), ctypes.byref(nb),
+                                                   ctypes.byref(ne)), None)
+        out = np.zeros(max(1, nb.value), dtype=np.int32)
+        inn = np.zeros(max(1, nb.value), dtype=np.int32)
+        off = np.zeros(max(1, nb.value), dtype=np.int64)
+        data = torch.zeros(max(1, ne.value), dtype=torch.float64, device="cuda")
+        self._check(self.lib.dmrg_su2_product(self.h, wptr, la, ra, int(tk1), int(tk2), int(tk), int(parity_b),
+                                              _ptr(out, ctypes.c_int32), _ptr(inn, ctypes.c_int32),
+                                              _ptr(off, ctypes.c_int64), _dev_ptr(data)), self.h)
+        return [(int(out[i]), int(inn[i]), int(off[i])) for i in range(nb.value)], data
 
     def su2_plan(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, precision="fp64"):
         """dmrg_su2_plan_create: a Su2Plan (arguments as in _su2_args;

@@ -20,6 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["kernels.hip", "kernels_bf16.hip", "kernels_pack.hip", "kernels_oz.hip", "engine.cpp",
            "gemm_mixed.cpp", "davidson.cpp", "truncate.cpp", "backward.cpp", "noalloc.hip", "su2.cpp",
+           "su2_product.hip",
            "capi.cpp"]
 ARCH = "gfx950"
 

@@ -14,6 +14,7 @@
 #include "davidson.h"
 #include "engine.h"
 #include "su2.h"
+#include "su2_product.h"
 #include "noalloc.h"
 #include "truncate.h"
 
@@ -659,6 +660,38 @@ dmrg_status dmrg_su2_plan_destroy(dmrg_ctx c, dmrg_su2_plan h) {
     DMRG_HIP(hipStreamSynchronize(c->stream));
     c->su2_plans.erase(h);
     delete h;
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_su2_product_size(const dmrg_su2_window* sectors, const dmrg_su2_operator* a,
+                                  const dmrg_su2_operator* b, int32_t two_k1, int32_t two_k2, int32_t two_k,
+                                  int32_t* n_blocks, int64_t* n_elems) {
+  return guarded(nullptr, [&]() -> dmrg_status {
+    DMRG_REQUIRE(sectors && a && b && n_blocks && n_elems, kErrInvalidArg, "su2_product_size: NULL pointer");
+    const Su2Product p = su2_product_plan(*sectors, *a, *b, two_k1, two_k2, two_k, 0);
+    *n_blocks = (int32_t)p.blocks.size();
+    *n_elems = p.size;
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_su2_product(dmrg_ctx c, const dmrg_su2_window* sectors, const dmrg_su2_operator* a,
+                             const dmrg_su2_operator* b, int32_t two_k1, int32_t two_k2, int32_t two_k,
+                             int32_t parity_b, int32_t* out_sector, int32_t* in_sector, int64_t* offset,
+                             double* data) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(sectors && a && b, kErrInvalidArg, "su2_product: NULL pointer");
+    const Su2Product p = su2_product_plan(*sectors, *a, *b, two_k1, two_k2, two_k, parity_b);
+    DMRG_REQUIRE(p.blocks.empty() || (out_sector && in_sector && offset), kErrInvalidArg,
+                 "su2_product: NULL output array");
+    for (size_t i = 0; i < p.blocks.size(); ++i) {
+      out_sector[i] = p.blocks[i].out;
+      in_sector[i] = p.blocks[i].in;
+      offset[i] = p.blocks[i].offset;
+    }
+    su2_product_run(p, *a, *b, data, c->stream);
     return kOk;
   });
 }

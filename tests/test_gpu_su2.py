@@ -284,3 +284,46 @@ def test_su2_operator_past_its_tensor_is_refused(ctx):
     ctx.su2_sigma(lsec, rsec, 2, 0, [([(0, 0, 0)], full)], [([(0, 0, 0)], ok, 0)], [(0, 0, 0, 0, 1.0)],
                   psi, out)
     assert torch.all(out == 0)
+
+
+def coupled_sector_keys(sec1, sec2):
+    """(i1, i2, 2S) of every coupled sector, in the library's numbering."""
+    keys = []
+    for i1, (_, s1, _) in enumerate(sec1):
+        for i2, (_, s2, _) in enumerate(sec2):
+            keys += [(i1, i2, ts) for ts in range(abs(s1 - s2), s1 + s2 + 1, 2)]
+    return keys
+
+
+@pytest.mark.parametrize("dn1,tk1,dn2,tk2,tk,site", [(1, 1, 0, 0, 1, True), (0, 0, 1, 1, 1, True),
+                                                     (1, 1, 1, 1, 0, True), (1, 1, -1, 1, 2, True),
+                                                     (0, 2, -1, 1, 3, True), (1, 1, 1, 1, 2, False),
+                                                     (0, 2, 0, 2, 2, False)])
+def test_su2_product_matches_the_oracle(ctx, dn1, tk1, dn2, tk2, tk, site):
+    """The renormalisation step's coupled product [A^k1 x B^k2]^k
+    (dmrg_su2_product) against the oracle's product_operator, block by
+    block: a block operator with sectors up to 120 multiplets times a
+    one-orbital site operator, or one with sectors up to 40 times a second
+    block's operator (sectors up to 6)."""
+    print(f"su2 product: dn1={dn1} 2k1={tk1} dn2={dn2} 2k2={tk2} 2k={tk} site={site}", flush=True)
+    rng = np.random.default_rng(11 + tk1 + 3 * tk + 5 * dn1)
+    sec1, _ = sector_window(8, 0, 120 if site else 40, rng)
+    # a one-orbital site, or a second block of small sectors (its blocks
+    # multiply the Kronecker products' sizes)
+    sec2 = [(0, 0, 1), (1, 1, 1), (2, 0, 1)] if site else sector_window(8, 0, 6, rng)[1]
+    t1 = random_operator(sec1, dn1, tk1, rng)
+    t2 = random_operator(sec2, dn2, tk2, rng, keep=1.0)
+    p2 = abs(dn2) % 2
+    want = su2.product_operator(sec1, sec2, t1, t2, tk1, tk2, tk, p2)
+    ops = device_ops([t1, t2])
+    blocks, data = ctx.su2_product(sec1, sec2, ops[0], ops[1], tk1, tk2, tk, p2)
+    torch_data = data.cpu().numpy()
+    keys = coupled_sector_keys(sec1, sec2)
+    nz = {k: v for k, v in want.items() if np.any(v != 0)}
+    assert len(blocks) == len(nz) > 0
+    scale = max(np.abs(v).max() for v in nz.values())
+    for out, inn, off in blocks:
+        k = (keys[out], keys[inn])
+        ref = nz[k]
+        got = torch_data[off:off + ref.size].reshape(ref.shape)
+        assert np.abs(got - ref).max() <= TOL * scale
