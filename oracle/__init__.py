@@ -18,10 +18,11 @@ blocksparse renormalised block operators, the normal/complementary sigma and
 truncation  the two-site truncation (per-sector SVD, global selection of the
             D largest weights, truncation error) and the window move.
 orbital     generalised Fock matrix and orbital gradient from the RDMs.
-su2         spin adaptation: Clebsch-Gordan and 6j coefficients, multiplet
-            bases of blocks, the spin-adapted window H_eff (plain
-            definition) and the scalar-product recoupling rule of a
-            spin-adapted sigma.
+su2         spin adaptation: Clebsch-Gordan, 6j and 9j coefficients,
+            multiplet bases of blocks, the spin-adapted window H_eff (plain
+            definition), the scalar-product recoupling rule of a
+            spin-adapted sigma and its block-by-block contraction, and the
+            coupled block x site operator product of the renormalisation.
 
 Every function is pinned by tests under tests/ (test_oracle_*.py) against
 closed forms, brute force or the plain definitions; the pins are listed in
