@@ -34,6 +34,8 @@ holds the plain definitions that a spin-adapted sigma has to reproduce:
   (enlarged-block) tensor operators of rank 0, 1/2 and 1, each a product of
   reduced block matrices weighted by this coefficient, which is what the
   grouped block GEMMs would execute.
+* rotate_operator: the renormalisation's projection of those blocks onto
+  the kept multiplets of each new (N, S) sector, O' = U^T X U by sector.
 * wigner_9j and product_coupling / product_operator: the reduced blocks of
   a coupled product [A^k1 x B^k2]^k of operators on two subsystems (a block
   operator times a site operator: the renormalisation step that builds the
@@ -55,7 +57,9 @@ orthogonality of the recoupling matrix it defines; product_operator against
 the coupled product built component by component on the Fock space, for
 ranks 0, 1/2, 1 and 3/2 and particle changes 0, +-1, 2 (a dropped (2S + 1)
 factor and a bra/ket exchange in the 9j symbol each fail it), and at k = 0
-against scalar_coupling.
+against scalar_coupling; product_operator followed by rotate_operator onto
+a truncated spin-adapted basis of block x site against the reduced elements
+of the Fock-space product between the kept multiplets.
 """
 from math import factorial, sqrt
 
@@ -177,6 +181,23 @@ def product_operator(sec1, sec2, t1, t2, tk1, tk2, tk, parity2):
                         continue
                     key = ((i1p, i2p, tS2), (i1, i2, tS))
                     out[key] = out.get(key, 0.0) + sign * c * np.kron(a, b)
+    return out
+
+
+def rotate_operator(blocks, proj, group_of):
+    """The renormalised reduced blocks: for coupled sectors cs grouped into
+    new sectors g (group_of[cs], or -1 for a sector kept out) with kept
+    multiplets spanned by the columns of proj[cs] (d_cs x D_g, the rows of
+    U_g that belong to cs), O[g', g] = sum over blocks X[cs', cs] of
+    proj[cs']^T X[cs', cs] proj[cs].  blocks: {(cs', cs): matrix};
+    returns {(g', g): matrix}."""
+    out = {}
+    for (c2, c), x in blocks.items():
+        g2, g = group_of[c2], group_of[c]
+        if g2 < 0 or g < 0:
+            continue
+        y = proj[c2].T @ x @ proj[c]
+        out[(g2, g)] = out.get((g2, g), 0.0) + y
     return out
 
 

@@ -381,3 +381,67 @@ def test_product_operator_against_the_fock_space(dn1, tk1, dn2, tk2, tk):
                     assert np.allclose(brute, want, atol=1e-11)
                     checked += int(np.abs(brute).max() > 1e-3)
     assert checked >= 3
+
+
+def test_renormalised_operator_against_the_fock_space():
+    """A block operator times a site operator, coupled (product_operator) and
+    projected onto a truncated spin-adapted basis of the enlarged block
+    (rotate_operator), against the reduced elements of the Fock-space
+    product between the kept multiplets (random orthonormal combinations of
+    the coupled states of each (N, S), fewer than all)."""
+    nl, nr = 2, 1
+    dn1, tk1, dn2, tk2, tk = 1, 1, 0, 2, 1
+    rng = np.random.default_rng(77)
+    left, right = su2.multiplets(nl), su2.multiplets(nr)
+    sec1 = [(M.n, M.tS, M.dim) for M in left]
+    sec2 = [(M.n, M.tS, M.dim) for M in right]
+    t1, A = block_tensor(left, nl, dn1, tk1, rng)
+    t2, B = block_tensor(right, nr, dn2, tk2, rng)
+    full_l = DetSpace.full(nl)
+    nL = np.bitwise_count(full_l.dets.astype(np.uint64)).astype(int)
+    sign = np.diag((-1.0) ** ((abs(dn2) % 2) * nL))
+    X = {tq: sum(su2.clebsch_gordan(tk1, q1, tk2, tq - q1, tk, tq) * np.kron(B[tq - q1], A[q1] @ sign)
+                 for q1 in range(-tk1, tk1 + 1, 2) if abs(tq - q1) <= tk2)
+         for tq in range(-tk, tk + 1, 2)}
+    blocks = su2.product_operator(sec1, sec2, t1, t2, tk1, tk2, tk, abs(dn2) % 2)
+    # coupled sectors (i1, i2, 2S), numbered as the library does, grouped by (N, 2S)
+    cs = [(i1, i2, ts) for i1, (_, s1, _) in enumerate(sec1) for i2, (_, s2, _) in enumerate(sec2)
+          for ts in range(abs(s1 - s2), s1 + s2 + 1, 2)]
+    groups = sorted({(sec1[i1][0] + sec2[i2][0], ts) for i1, i2, ts in cs})
+    group_of = [groups.index((sec1[i1][0] + sec2[i2][0], ts)) for i1, i2, ts in cs]
+    U, proj = {}, {}
+    for g, (n, ts) in enumerate(groups):
+        members = [c for c in range(len(cs)) if group_of[c] == g]
+        dim = sum(sec1[cs[c][0]][2] * sec2[cs[c][1]][2] for c in members)
+        keep = max(1, dim - 1) if dim > 1 else 1
+        U[g] = np.linalg.qr(rng.normal(size=(dim, dim)))[0][:, :keep]
+        r = 0
+        for c in members:
+            d = sec1[cs[c][0]][2] * sec2[cs[c][1]][2]
+            proj[c] = U[g][r:r + d]
+            r += d
+    keyed = {(cs.index(k2), cs.index(k)): v for (k2, k), v in blocks.items()}
+    got = su2.rotate_operator(keyed, proj, group_of)
+
+    def kept_vectors(g, tM):
+        n, ts = groups[g]
+        basis = su2.coupled_basis(left, right, n, ts)  # (ia, al, ib, be), (ia, ib) outer: the coupled sectors in order
+        P, space = su2.coupled_vectors(left, right, nl, nr, n, ts, tM, basis)
+        return P @ U[g], space
+
+    checked = 0
+    for (g2, g), o in got.items():
+        (n2, ts2), (n, ts) = groups[g2], groups[g]
+        V, sk = kept_vectors(g, ts)
+        for tq in range(-tk, tk + 1, 2):
+            tM2 = ts + tq
+            if abs(tM2) > ts2:
+                continue
+            cg = su2.clebsch_gordan(ts, ts, tk, tq, ts2, tM2)
+            if abs(cg) < 1e-12:
+                continue
+            V2, sb = kept_vectors(g2, tM2)
+            brute = V2.T @ X[tq][np.ix_(np.asarray(sb.dets), np.asarray(sk.dets))] @ V / cg
+            assert np.allclose(brute, o, atol=1e-11)
+            checked += 1
+    assert checked >= 5
