@@ -489,6 +489,38 @@ dmrg_status dmrg_su2_product(dmrg_ctx ctx, const dmrg_su2_window* sectors, const
                              int32_t parity_b, int32_t* out_sector, int32_t* in_sector, int64_t* offset,
                              double* data);
 
+/* The renormalisation's projection onto the kept multiplets: the coupled
+ * sectors c of the enlarged block (as numbered by dmrg_su2_product) are
+ * grouped into new sectors g of one (N, S) each; the kept multiplets of g
+ * are the columns of U_g (rows: the multiplets of g's coupled sectors in
+ * their order), and proj[c] is the block of U_g's rows that belong to c
+ * (d_c x D_g, row-major, device).  For operator blocks X[c', c] the result
+ * is O[g', g] = sum over the blocks with c' in g' and c in g of
+ * proj[c']^T X[c', c] proj[c] (D_g' x D_g), by two stages of the FP64
+ * grouped GEMM.  Output blocks are ordered by g', then g. */
+typedef struct {
+  int32_t n_coupled;
+  const int32_t* coupled_dim;   /* host, n_coupled: multiplets of each coupled sector */
+  const int32_t* coupled_group; /* host, n_coupled: its new sector, or -1 if kept out */
+  int32_t n_groups;
+  const int32_t* group_dim;     /* host, n_groups: kept multiplets D_g */
+  const double* const* proj;    /* host array of n_coupled device pointers (NULL where kept out) */
+} dmrg_su2_basis;
+
+/* Number of output blocks and elements (host only; proj is not read).
+ * Errors: DMRG_ERR_INVALID_ARG for a sector or group index out of range or
+ * a non-positive dimension. */
+dmrg_status dmrg_su2_rotate_size(const dmrg_su2_basis* basis, int32_t n_blocks, const int32_t* out_sector,
+                                 const int32_t* in_sector, int32_t* n_out, int64_t* n_elems);
+
+/* Writes the output blocks' groups and element offsets (host arrays of
+ * n_out) and data (device, n_elems); X is given as dmrg_su2_product
+ * returns it (host sector and offset arrays, device data).  Synchronises
+ * the context stream (its workspace is released on return). */
+dmrg_status dmrg_su2_rotate(dmrg_ctx ctx, const dmrg_su2_basis* basis, int32_t n_blocks, const int32_t* out_sector,
+                            const int32_t* in_sector, const int64_t* offset, const double* data,
+                            int32_t* out_group, int32_t* in_group, int64_t* out_offset, double* out_data);
+
 /* Diagnostic: copies diag(H_eff) of the current window (the Davidson
  * preconditioner; psi layout, device pointer, length dmrg_psi_size). */
 dmrg_status dmrg_debug_diag(dmrg_ctx ctx, double* out);

@@ -101,6 +101,12 @@ class Su2Info(ctypes.Structure):
                 ("flops_stage1", ctypes.c_double), ("flops_stage2", ctypes.c_double)]
 
 
+class Su2Basis(ctypes.Structure):
+    _fields_ = [("n_coupled", ctypes.c_int32), ("coupled_dim", ctypes.POINTER(ctypes.c_int32)),
+                ("coupled_group", ctypes.POINTER(ctypes.c_int32)), ("n_groups", ctypes.c_int32),
+                ("group_dim", ctypes.POINTER(ctypes.c_int32)), ("proj", ctypes.POINTER(ctypes.c_void_p))]
+
+
 class Su2Pair(ctypes.Structure):
     _fields_ = [("left_op", ctypes.c_int32), ("right_op", ctypes.c_int32), ("two_k", ctypes.c_int32),
                 ("parity", ctypes.c_int32), ("coef", ctypes.c_double)]
@@ -159,6 +165,14 @@ EXPORTS = {
                                           ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
                                           ctypes.c_void_p]),
+    "dmrg_su2_rotate_size": (ctypes.c_int32, [ctypes.POINTER(Su2Basis), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_int64)]),
+    "dmrg_su2_rotate": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(Su2Basis), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "dmrg_debug_gemm": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -643,6 +657,53 @@ class Context:
                                               _ptr(out, ctypes.c_int32), _ptr(inn, ctypes.c_int32),
                                               _ptr(off, ctypes.c_int64), _dev_ptr(data)), self.h)
         return [(int(out[i]), int(inn[i]), int(off[i])) for i in range(nb.value)], data
+
+    def su2_rotate(self, blocks, data, coupled_dims, coupled_group, group_dims, proj):
+        """dmrg_su2_rotate: blocks [(out coupled sector, in coupled sector,
+        offset)] and their float64 CUDA data (as su2_product returns them),
+        the coupled sectors' dimensions and new sectors (-1: kept out), the
+        kept dimension of each new sector, and proj[c] a float64 CUDA tensor
+        of d_c x D_g (None where kept out).  Returns (blocks [(g', g,
+        offset)], float64 CUDA tensor)."""
+        import torch
+        cd = np.ascontiguousarray(coupled_dims, dtype=np.int32)
+        cg = np.ascontiguousarray(coupled_group, dtype=np.int32)
+        gd = np.ascontiguousarray(group_dims, dtype=np.int32)
+        if len(cd) != len(cg) or len(proj) != len(cd):
+            raise ValueError("one dimension, group and projector per coupled sector")
+        ptrs = (ctypes.c_void_p * max(1, len(proj)))()
+        for c, pt in enumerate(proj):
+            if pt is None:
+                if cg[c] >= 0:
+                    raise ValueError(f"coupled sector {c} is kept but has no projector")
+                continue
+            if tuple(pt.shape) != (int(cd[c]), int(gd[cg[c]])):
+                raise ValueError(f"projector {c} must be {cd[c]} x {gd[cg[c]]}")
+            ptrs[c] = _dev_ptr(pt).value
+        basis = Su2Basis(len(cd), _ptr(cd, ctypes.c_int32), _ptr(cg, ctypes.c_int32), len(gd),
+                         _ptr(gd, ctypes.c_int32), ptrs)
+        b = np.asarray(blocks, dtype=np.int64).reshape(-1, 3)
+        bo = np.ascontiguousarray(b[:, 0], dtype=np.int32)
+        bi = np.ascontiguousarray(b[:, 1], dtype=np.int32)
+        boff = np.ascontiguousarray(b[:, 2])
+        for k in range(len(b)):  # every block inside the data tensor
+            if not (0 <= bo[k] < len(cd) and 0 <= bi[k] < len(cd)):
+                raise ValueError(f"block {k}: coupled sector out of range")
+            if boff[k] < 0 or boff[k] + int(cd[bo[k]]) * int(cd[bi[k]]) > data.numel():
+                raise ValueError(f"block {k} reaches past its data tensor")
+        nb, ne = ctypes.c_int32(), ctypes.c_int64()
+        self._check(self.lib.dmrg_su2_rotate_size(ctypes.byref(basis), len(b), _ptr(bo, ctypes.c_int32),
+                                                  _ptr(bi, ctypes.c_int32), ctypes.byref(nb), ctypes.byref(ne)),
+                    None)
+        og = np.zeros(max(1, nb.value), dtype=np.int32)
+        ig = np.zeros(max(1, nb.value), dtype=np.int32)
+        oo = np.zeros(max(1, nb.value), dtype=np.int64)
+        out = torch.zeros(max(1, ne.value), dtype=torch.float64, device="cuda")
+        self._check(self.lib.dmrg_su2_rotate(self.h, ctypes.byref(basis), len(b), _ptr(bo, ctypes.c_int32),
+                                             _ptr(bi, ctypes.c_int32), _ptr(boff, ctypes.c_int64), _dev_ptr(data),
+                                             _ptr(og, ctypes.c_int32), _ptr(ig, ctypes.c_int32),
+                                             _ptr(oo, ctypes.c_int64), _dev_ptr(out)), self.h)
+        return [(int(og[i]), int(ig[i]), int(oo[i])) for i in range(nb.value)], out
 
     def su2_plan(self, left_sectors, right_sectors, n_elec, two_s, left_ops, right_ops, pairs, precision="fp64"):
         """dmrg_su2_plan_create: a Su2Plan (arguments as in _su2_args;

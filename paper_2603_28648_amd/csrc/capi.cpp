@@ -696,6 +696,36 @@ dmrg_status dmrg_su2_product(dmrg_ctx c, const dmrg_su2_window* sectors, const d
   });
 }
 
+dmrg_status dmrg_su2_rotate_size(const dmrg_su2_basis* basis, int32_t n_blocks, const int32_t* out_sector,
+                                 const int32_t* in_sector, int32_t* n_out, int64_t* n_elems) {
+  return guarded(nullptr, [&]() -> dmrg_status {
+    DMRG_REQUIRE(basis && n_out && n_elems, kErrInvalidArg, "su2_rotate_size: NULL pointer");
+    const Su2Rotation r = su2_rotation_plan(*basis, n_blocks, out_sector, in_sector);
+    *n_out = (int32_t)r.outs.size();
+    *n_elems = r.size;
+    return kOk;
+  });
+}
+
+dmrg_status dmrg_su2_rotate(dmrg_ctx c, const dmrg_su2_basis* basis, int32_t n_blocks, const int32_t* out_sector,
+                            const int32_t* in_sector, const int64_t* offset, const double* data,
+                            int32_t* out_group, int32_t* in_group, int64_t* out_offset, double* out_data) {
+  if (!c) return fail(c, kErrInvalidArg, "ctx is NULL");
+  return guarded(c, [&]() -> dmrg_status {
+    DMRG_REQUIRE(basis, kErrInvalidArg, "su2_rotate: NULL basis");
+    const Su2Rotation r = su2_rotation_plan(*basis, n_blocks, out_sector, in_sector);
+    DMRG_REQUIRE(r.outs.empty() || (out_group && in_group && out_offset), kErrInvalidArg,
+                 "su2_rotate: NULL output array");
+    for (size_t i = 0; i < r.outs.size(); ++i) {
+      out_group[i] = r.outs[i].g2;
+      in_group[i] = r.outs[i].g;
+      out_offset[i] = r.outs[i].offset;
+    }
+    su2_rotation_run(r, *basis, out_sector, in_sector, offset, data, out_data, c->stream);
+    return kOk;
+  });
+}
+
 dmrg_status dmrg_debug_gemm(dmrg_ctx c, int32_t m, int32_t n, int32_t k, const double* a,
                             int32_t lda, int32_t trans_a, const double* b, int32_t ldb,
                             int32_t trans_b, double* cc, int32_t ldc, double alpha, int32_t beta,

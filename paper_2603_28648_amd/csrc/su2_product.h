@@ -31,4 +31,22 @@ Su2Product su2_product_plan(const dmrg_su2_window& w, const dmrg_su2_operator& a
 void su2_product_run(const Su2Product& p, const dmrg_su2_operator& a, const dmrg_su2_operator& b, double* data,
                      hipStream_t s);
 
+// The projection onto the kept multiplets (dmrg_su2_rotate): output blocks
+// (g', g) with their offsets, and per output the input blocks it sums.
+struct Su2Rotation {
+  struct Out {
+    int g2, g;
+    int64_t offset;
+    std::vector<int> blocks;
+  };
+  std::vector<Out> outs;
+  int64_t size = 0;
+};
+Su2Rotation su2_rotation_plan(const dmrg_su2_basis& basis, int n_blocks, const int32_t* out_sector,
+                              const int32_t* in_sector);
+// Writes the rotated blocks (device); synchronises the stream.
+void su2_rotation_run(const Su2Rotation& r, const dmrg_su2_basis& basis, const int32_t* out_sector,
+                      const int32_t* in_sector, const int64_t* offset, const double* data, double* out,
+                      hipStream_t s);
+
 }  // namespace dmrg

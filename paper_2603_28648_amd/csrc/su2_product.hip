@@ -1,14 +1,17 @@
 // Renormalisation step of spin-adapted operators: the reduced blocks of a
 // coupled product [A^k1 x B^k2]^k of operators on two subsystems (block and
-// site).  Every output block is the Kronecker product of one block of A and
+// site), and their projection onto the kept multiplets of the enlarged
+// block.  Every output block is the Kronecker product of one block of A and
 // one block of B times the 9j-weighted coupling factor and the fermion sign
 // (see dmrg_su2_product in include/dmrg.h); one workgroup writes each block.
 #include "su2_product.h"
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <vector>
 
+#include "gemm.h"
 #include "su2.h"
 
 namespace dmrg {
@@ -137,6 +140,68 @@ void su2_product_run(const Su2Product& p, const dmrg_su2_operator& a, const dmrg
   }
   DMRG_HIP(hipGetLastError());
   DMRG_HIP(hipStreamSynchronize(s));  // the task list is released on return
+}
+
+Su2Rotation su2_rotation_plan(const dmrg_su2_basis& basis, int n_blocks, const int32_t* out_sector,
+                              const int32_t* in_sector) {
+  const int nc = basis.n_coupled, ng = basis.n_groups;
+  DMRG_REQUIRE(nc >= 0 && ng >= 0 && (nc == 0 || (basis.coupled_dim && basis.coupled_group)) &&
+                   (ng == 0 || basis.group_dim),
+               kErrInvalidArg, "su2_rotate: NULL basis array");
+  for (int c = 0; c < nc; ++c)
+    DMRG_REQUIRE(basis.coupled_dim[c] > 0 && basis.coupled_group[c] >= -1 && basis.coupled_group[c] < ng,
+                 kErrInvalidArg, "su2_rotate: coupled sector with a bad dimension or group");
+  for (int g = 0; g < ng; ++g)
+    DMRG_REQUIRE(basis.group_dim[g] > 0, kErrInvalidArg, "su2_rotate: a new sector needs kept multiplets");
+  DMRG_REQUIRE(n_blocks >= 0 && (n_blocks == 0 || (out_sector && in_sector)), kErrInvalidArg,
+               "su2_rotate: NULL block array");
+  std::map<std::pair<int, int>, std::vector<int>> by;
+  for (int j = 0; j < n_blocks; ++j) {
+    DMRG_REQUIRE(out_sector[j] >= 0 && out_sector[j] < nc && in_sector[j] >= 0 && in_sector[j] < nc,
+                 kErrInvalidArg, "su2_rotate: block sector out of range");
+    const int g2 = basis.coupled_group[out_sector[j]], g = basis.coupled_group[in_sector[j]];
+    if (g2 >= 0 && g >= 0) by[{g2, g}].push_back(j);
+  }
+  Su2Rotation r;
+  for (auto& kv : by) {
+    r.outs.push_back({kv.first.first, kv.first.second, r.size, kv.second});
+    r.size += (int64_t)basis.group_dim[kv.first.first] * basis.group_dim[kv.first.second];
+  }
+  return r;
+}
+
+void su2_rotation_run(const Su2Rotation& r, const dmrg_su2_basis& basis, const int32_t* out_sector,
+                      const int32_t* in_sector, const int64_t* offset, const double* data, double* out,
+                      hipStream_t s) {
+  if (r.outs.empty()) return;
+  DMRG_REQUIRE(basis.proj && data && out && offset, kErrInvalidArg, "su2_rotate: NULL data");
+  const int32_t* dim = basis.coupled_dim;
+  const int32_t* D = basis.group_dim;
+  // stage 1: Y_j = X_j proj[in] (d_out x D_g), one problem per block
+  int64_t ws = 0;
+  for (const auto& o : r.outs)
+    for (int j : o.blocks) ws += (int64_t)dim[out_sector[j]] * D[o.g];
+  DevBuf buf((size_t)std::max<int64_t>(ws, 1) * sizeof(double));
+  double* Y = buf.as<double>();
+  GemmBatch b1, b2;
+  int64_t at = 0;
+  for (const auto& o : r.outs) {
+    const size_t s2 = b2.segs.size();
+    for (int j : o.blocks) {
+      const int c2 = out_sector[j], c = in_sector[j];
+      DMRG_REQUIRE(basis.proj[c] && basis.proj[c2], kErrInvalidArg, "su2_rotate: NULL projector of a kept sector");
+      const size_t s0 = b1.segs.size();
+      b1.segs.push_back({data + offset[j], basis.proj[c], dim[c], D[o.g], dim[c], 0, 1.0});
+      b1.add_problem(Y + at, D[o.g], dim[c2], D[o.g], s0, s0 + 1, 0);
+      // stage 2: O[g', g] += proj[c']^T Y_j
+      b2.segs.push_back({basis.proj[c2], Y + at, D[o.g2], D[o.g], dim[c2], kTransA, 1.0});
+      at += (int64_t)dim[c2] * D[o.g];
+    }
+    b2.add_problem(out + o.offset, D[o.g], D[o.g2], D[o.g], s2, b2.segs.size(), 0);
+  }
+  launch_gemm_f64(b1, s);
+  launch_gemm_f64(b2, s);
+  DMRG_HIP(hipStreamSynchronize(s));  // the workspace is released on return
 }
 
 }  // namespace dmrg

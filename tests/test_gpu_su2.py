@@ -327,3 +327,46 @@ def test_su2_product_matches_the_oracle(ctx, dn1, tk1, dn2, tk2, tk, site):
         ref = nz[k]
         got = torch_data[off:off + ref.size].reshape(ref.shape)
         assert np.abs(got - ref).max() <= TOL * scale
+
+
+@pytest.mark.parametrize("dn1,tk1,dn2,tk2,tk,seed", [(1, 1, 0, 2, 1, 1), (1, 1, -1, 1, 2, 2), (0, 2, 1, 1, 1, 3)])
+def test_su2_renormalisation_matches_the_oracle(ctx, dn1, tk1, dn2, tk2, tk, seed):
+    """The renormalisation of a block operator times a site operator: the
+    coupled product (dmrg_su2_product) projected onto a truncated basis of
+    every (N, S) sector of the enlarged block (dmrg_su2_rotate), against the
+    oracle's product_operator and rotate_operator."""
+    print(f"su2 renormalisation: dn1={dn1} 2k1={tk1} dn2={dn2} 2k2={tk2} 2k={tk} seed={seed}", flush=True)
+    rng = np.random.default_rng(100 + seed)
+    sec1, _ = sector_window(8, 0, 90, rng)
+    sec2 = [(0, 0, 1), (1, 1, 1), (2, 0, 1)]
+    t1 = random_operator(sec1, dn1, tk1, rng)
+    t2 = random_operator(sec2, dn2, tk2, rng, keep=1.0)
+    p2 = abs(dn2) % 2
+    ops = device_ops([t1, t2])
+    blocks, data = ctx.su2_product(sec1, sec2, ops[0], ops[1], tk1, tk2, tk, p2)
+    keys = coupled_sector_keys(sec1, sec2)
+    cdim = [sec1[i1][2] * sec2[i2][2] for i1, i2, _ in keys]
+    groups = sorted({(sec1[i1][0] + sec2[i2][0], ts) for i1, i2, ts in keys})
+    cgroup = [groups.index((sec1[i1][0] + sec2[i2][0], ts)) for i1, i2, ts in keys]
+    gsize = [sum(cdim[c] for c in range(len(keys)) if cgroup[c] == g) for g in range(len(groups))]
+    gdim = [max(1, (3 * n) // 4) for n in gsize]  # truncated: three quarters of each sector kept
+    cgroup = [g if g % 5 else -1 for g in cgroup]  # every fifth new sector kept out
+    proj_np, row = [], [0] * len(groups)
+    U = [rng.normal(size=(gsize[g], gdim[g])) for g in range(len(groups))]
+    for c in range(len(keys)):
+        g = groups.index((sec1[keys[c][0]][0] + sec2[keys[c][1]][0], keys[c][2]))
+        proj_np.append(U[g][row[g]:row[g] + cdim[c]] if cgroup[c] >= 0 else None)
+        row[g] += cdim[c]
+    proj = [dev(p) if p is not None else None for p in proj_np]
+    out_blocks, out = ctx.su2_rotate(blocks, data, cdim, cgroup, gdim, proj)
+    want_prod = su2.product_operator(sec1, sec2, t1, t2, tk1, tk2, tk, p2)
+    index = {k: i for i, k in enumerate(keys)}
+    keyed = {(index[k2], index[k]): v for (k2, k), v in want_prod.items() if np.any(v != 0)}
+    want = {k: v for k, v in su2.rotate_operator(keyed, proj_np, cgroup).items()}
+    got_np = out.cpu().numpy()
+    assert len(out_blocks) == len(want) > 0
+    scale = max(np.abs(v).max() for v in want.values())
+    for g2, g, off in out_blocks:
+        ref = want[(g2, g)]
+        got = got_np[off:off + ref.size].reshape(ref.shape)
+        assert np.abs(got - ref).max() <= TOL * scale

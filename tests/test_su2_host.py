@@ -93,3 +93,31 @@ def test_product_size_matches_the_oracle_blocks(dn1, tk1, dn2, tk2, tk):
                                      ctypes.byref(nb), ctypes.byref(ne)) == 0
     assert nb.value == len(want) > 0
     assert ne.value == sum(v.size for v in want.values())
+
+
+def test_rotate_size_and_errors():
+    """dmrg_su2_rotate_size (host only): one output per pair of kept new
+    sectors that receives a block, D_g' x D_g elements each; bad indices are
+    errors."""
+    import ctypes
+    from paper_2603_28648_amd._binding import Su2Basis, load_library, _ptr
+    lib = load_library()
+    cd = np.array([2, 3, 1, 4], dtype=np.int32)
+    cg = np.array([0, 0, 1, -1], dtype=np.int32)
+    gd = np.array([4, 1], dtype=np.int32)
+    ptrs = (ctypes.c_void_p * 4)()
+    basis = Su2Basis(4, _ptr(cd, ctypes.c_int32), _ptr(cg, ctypes.c_int32), 2, _ptr(gd, ctypes.c_int32), ptrs)
+    bo = np.array([0, 1, 2, 3, 2], dtype=np.int32)
+    bi = np.array([1, 2, 0, 0, 2], dtype=np.int32)
+    nb, ne = ctypes.c_int32(), ctypes.c_int64()
+    assert lib.dmrg_su2_rotate_size(ctypes.byref(basis), 5, _ptr(bo, ctypes.c_int32), _ptr(bi, ctypes.c_int32),
+                                    ctypes.byref(nb), ctypes.byref(ne)) == 0
+    # (0,0) from blocks 0; (0,1) from block 1; (1,0) from block 2; (1,1) from block 4; block 3 is kept out
+    assert nb.value == 4 and ne.value == 4 * 4 + 4 * 1 + 1 * 4 + 1 * 1
+    bad = np.array([4, 1, 2, 3, 2], dtype=np.int32)
+    assert lib.dmrg_su2_rotate_size(ctypes.byref(basis), 5, _ptr(bad, ctypes.c_int32), _ptr(bi, ctypes.c_int32),
+                                    ctypes.byref(nb), ctypes.byref(ne)) == -1
+    cg_bad = np.array([0, 0, 2, -1], dtype=np.int32)
+    basis_bad = Su2Basis(4, _ptr(cd, ctypes.c_int32), _ptr(cg_bad, ctypes.c_int32), 2, _ptr(gd, ctypes.c_int32), ptrs)
+    assert lib.dmrg_su2_rotate_size(ctypes.byref(basis_bad), 5, _ptr(bo, ctypes.c_int32), _ptr(bi, ctypes.c_int32),
+                                    ctypes.byref(nb), ctypes.byref(ne)) == -1
