@@ -370,3 +370,21 @@ def test_su2_renormalisation_matches_the_oracle(ctx, dn1, tk1, dn2, tk2, tk, see
         ref = want[(g2, g)]
         got = got_np[off:off + ref.size].reshape(ref.shape)
         assert np.abs(got - ref).max() <= TOL * scale
+
+
+def test_su2_rotate_refuses_bad_projectors(ctx):
+    """The binding checks projector shapes and block ranges before the
+    library sees the pointers (no kernel runs)."""
+    import torch
+    data = torch.zeros(8, dtype=torch.float64, device="cuda")
+    cdim, cgroup, gdim = [2, 2], [0, 0], [3]
+    good = [torch.zeros(2, 3, dtype=torch.float64, device="cuda") for _ in range(2)]
+    bad = [torch.zeros(2, 2, dtype=torch.float64, device="cuda"), good[1]]
+    with pytest.raises(ValueError):  # projector of the wrong shape
+        ctx.su2_rotate([(0, 1, 0)], data, cdim, cgroup, gdim, bad)
+    with pytest.raises(ValueError):  # a kept sector without a projector
+        ctx.su2_rotate([(0, 1, 0)], data, cdim, cgroup, gdim, [None, good[1]])
+    with pytest.raises(ValueError):  # a block past the data tensor
+        ctx.su2_rotate([(0, 1, 6)], data, cdim, cgroup, gdim, good)
+    blocks, out = ctx.su2_rotate([(0, 1, 0), (1, 0, 4)], data, cdim, cgroup, gdim, good)
+    assert blocks == [(0, 0, 0)] and torch.all(out == 0)
