@@ -34,6 +34,10 @@ holds the plain definitions that a spin-adapted sigma has to reproduce:
   (enlarged-block) tensor operators of rank 0, 1/2 and 1, each a product of
   reduced block matrices weighted by this coefficient, which is what the
   grouped block GEMMs would execute.
+* window_pairs: the window Hamiltonian written as scalar products of left
+  unit tensors and their right partner operators (an expansion over the
+  left block's operator space), the input contract_scalar_products needs
+  to apply H_eff.
 * rotate_operator: the renormalisation's projection of those blocks onto
   the kept multiplets of each new (N, S) sector, O' = U^T X U by sector.
 * wigner_9j and product_coupling / product_operator: the reduced blocks of
@@ -59,7 +63,9 @@ ranks 0, 1/2, 1 and 3/2 and particle changes 0, +-1, 2 (a dropped (2S + 1)
 factor and a bra/ket exchange in the 9j symbol each fail it), and at k = 0
 against scalar_coupling; product_operator followed by rotate_operator onto
 a truncated spin-adapted basis of block x site against the reduced elements
-of the Fock-space product between the kept multiplets.
+of the Fock-space product between the kept multiplets; window_pairs
+contracted by contract_scalar_products against heff_su2 (four windows of
+four orbitals split 2 | 2; a phase error in the recoupling rule fails it).
 """
 from math import factorial, sqrt
 
@@ -314,6 +320,85 @@ def heff_su2(h, eri, left, right, n_left, n_right, n, tS, tM=None):
     P, space = coupled_vectors(left, right, n_left, n_right, n, tS, tM, basis)
     H = space.hamiltonian(h, eri).toarray()
     return P.T @ H @ P, basis
+
+
+def window_pairs(h, eri, left, right, n_left, n_right):
+    """The window Hamiltonian as a sum of scalar products [U^k x V^k]^0 of a
+    left and a right tensor operator, for complete multiplet bases of both
+    blocks (an expansion over the left operator space, written out):
+
+    * H on the n_left + n_right orbitals in the product basis |l>|r> (left
+      determinant in the low bits) is sum over left basis states of
+      |l'><l| (x) R(l', l), with R(l', l) = <l'| H |l> the right-block
+      operator;
+    * in the multiplet basis of the left block, |a' M'><a M| =
+      sum over k of (2k + 1) / (2S_a' + 1) <S_a M; k q | S_a' M'> U^k_q,
+      U^k the unit tensor with reduced element 1 between (a', alpha') and
+      (a, alpha) (orthogonality of the Clebsch-Gordan coefficients over M);
+    * so H = sum over (a' alpha', a alpha, k) of sum_q U^k_q W^k_q, and
+      V^k_-q = W^k_q / <k q; k -q | 0 0> makes each term the scalar
+      product [U^k x V^k]^0; V^k's reduced blocks on the right multiplets
+      follow from one non-zero Clebsch-Gordan coefficient each.
+
+    The products are taken in the product basis itself, so no fermion sign
+    is added (parity 0).  Returns pairs (1, 2k, 0, {(a', a): unit block},
+    {(b', b): reduced block of V^k}) for contract_scalar_products."""
+    K = n_left + n_right
+    H = DetSpace.full(K).hamiltonian(h, eri).toarray()
+    dl, dr = 1 << (2 * n_left), 1 << (2 * n_right)
+    H4 = H.reshape(dr, dl, dr, dl)  # [r', l', r, l]: index = l + dl r
+
+    def state_vectors(mults, n_orb):
+        full = DetSpace.full(n_orb)
+        out = {}
+        for i, M in enumerate(mults):
+            for tM in range(-M.tS, M.tS + 1, 2):
+                V = np.zeros((full.dim, M.dim))
+                V[full.index(M.space[tM].dets)] = M.vec[tM]
+                out[(i, tM)] = V
+        return out
+
+    lv, rv = state_vectors(left, n_left), state_vectors(right, n_right)
+    pairs = []
+    for ia2, A2 in enumerate(left):
+        for ia, A in enumerate(left):
+            for al2 in range(A2.dim):
+                for al in range(A.dim):
+                    for tk in range(abs(A2.tS - A.tS), A2.tS + A.tS + 1, 2):
+                        V = {}
+                        for tM in range(-A.tS, A.tS + 1, 2):
+                            for tM2 in range(-A2.tS, A2.tS + 1, 2):
+                                tq = tM2 - tM
+                                if abs(tq) > tk:
+                                    continue
+                                cg = clebsch_gordan(A.tS, tM, tk, tq, A2.tS, tM2)
+                                if cg == 0.0:
+                                    continue
+                                R = np.einsum("a,xayb,b->xy", lv[(ia2, tM2)][:, al2], H4, lv[(ia, tM)][:, al])
+                                w = (tk + 1) / (A2.tS + 1) * cg / clebsch_gordan(tk, tq, tk, -tq, 0, 0)
+                                V[-tq] = V.get(-tq, 0.0) + w * R
+                        B = {}
+                        for ib2, B2 in enumerate(right):
+                            for ib, B1 in enumerate(right):
+                                if not _triangle(B1.tS, tk, B2.tS):
+                                    continue
+                                pick = next(((tMb, tq) for tMb in range(-B1.tS, B1.tS + 1, 2)
+                                             for tq in range(-tk, tk + 1, 2)
+                                             if tq in V and abs(tMb + tq) <= B2.tS
+                                             and abs(clebsch_gordan(B1.tS, tMb, tk, tq, B2.tS, tMb + tq)) > 1e-8),
+                                            None)
+                                if pick is None:
+                                    continue
+                                tMb, tq = pick
+                                cg = clebsch_gordan(B1.tS, tMb, tk, tq, B2.tS, tMb + tq)
+                                blk = rv[(ib2, tMb + tq)].T @ V[tq] @ rv[(ib, tMb)] / cg
+                                if np.abs(blk).max() > 1e-13:
+                                    B[(ib2, ib)] = blk
+                        if B:
+                            unit = np.zeros((A2.dim, A.dim))
+                            unit[al2, al] = 1.0
+                            pairs.append((1.0, tk, 0, {(ia2, ia): unit}, B))
+    return pairs
 
 
 def sigma_su2(h, eri, left, right, n_left, n_right, n, tS, psi):

@@ -388,3 +388,33 @@ def test_su2_rotate_refuses_bad_projectors(ctx):
         ctx.su2_rotate([(0, 1, 6)], data, cdim, cgroup, gdim, good)
     blocks, out = ctx.su2_rotate([(0, 1, 0), (1, 0, 4)], data, cdim, cgroup, gdim, good)
     assert blocks == [(0, 0, 0)] and torch.all(out == 0)
+
+
+@pytest.mark.parametrize("n,tS", [(4, 0), (4, 2), (3, 1)])
+def test_su2_sigma_of_the_window_hamiltonian(ctx, n, tS):
+    """The library's spin-adapted sigma (dmrg_su2_sigma) with the window
+    Hamiltonian's scalar products (oracle window_pairs, four orbitals split
+    2 | 2) equals the spin-adapted H_eff by its definition, whose spectrum
+    is the full-CI spectrum of spin S."""
+    from synthetic import make_integrals
+    K, nl = 4, 2
+    h, eri = make_integrals(K, K)
+    left, right = su2.multiplets(nl), su2.multiplets(K - nl)
+    lsec = [(M.n, M.tS, M.dim) for M in left]
+    rsec = [(M.n, M.tS, M.dim) for M in right]
+    pairs = su2.window_pairs(h, eri, left, right, nl, K - nl)
+    m, basis = su2.heff_su2(h, eri, left, right, nl, K - nl, n, tS)
+    psi_flat = np.random.default_rng(9 + n).normal(size=len(basis))
+    blocks = su2.coupled_blocks(lsec, rsec, n, tS)
+    psi = {k: np.zeros((lsec[k[0]][2], rsec[k[1]][2])) for k in blocks}
+    for c, (ia, al, ib, be) in enumerate(basis):
+        psi[(ia, ib)][al, be] = psi_flat[c]
+    packed = pack(lsec, rsec, n, tS, psi)
+    lops = [p[3] for p in pairs]
+    rops = [p[4] for p in pairs]
+    lib_pairs = [(i, i, p[1], p[2], p[0]) for i, p in enumerate(pairs)]
+    got = unpack(lsec, rsec, n, tS, run(ctx, lsec, rsec, n, tS, lops, rops, lib_pairs, packed))
+    got_flat = np.array([got[(ia, ib)][al, be] for (ia, al, ib, be) in basis])
+    ref = m @ psi_flat
+    assert np.abs(ref).max() > 1e-2
+    assert np.abs(got_flat - ref).max() <= TOL * np.abs(ref).max()

@@ -445,3 +445,34 @@ def test_renormalised_operator_against_the_fock_space():
             assert np.allclose(brute, o, atol=1e-11)
             checked += 1
     assert checked >= 5
+
+
+@pytest.mark.parametrize("K,nl,n,tS", [(4, 2, 4, 0), (4, 2, 4, 2), (4, 2, 3, 1), (4, 2, 5, 3)])
+def test_window_hamiltonian_as_scalar_products(K, nl, n, tS):
+    """The window Hamiltonian expanded into scalar products of left unit
+    tensors and right partner operators (window_pairs), contracted block by
+    block with the spin-adapted rule (contract_scalar_products, the
+    contraction the library runs), equals the spin-adapted H_eff by its
+    definition (heff_su2, whose spectrum is the full-CI spectrum of that
+    spin)."""
+    h, eri = make_integrals(K, K)
+    left, right = su2.multiplets(nl), su2.multiplets(K - nl)
+    lsec = [(M.n, M.tS, M.dim) for M in left]
+    rsec = [(M.n, M.tS, M.dim) for M in right]
+    pairs = su2.window_pairs(h, eri, left, right, nl, K - nl)
+    # ranks 0, 1/2 and 1 (doubled 0, 1, 2): a term of H moves at most two
+    # electrons' worth of spin across the cut; higher-rank unit tensors get
+    # no partner
+    assert {p[1] for p in pairs} == {0, 1, 2}
+    m, basis = su2.heff_su2(h, eri, left, right, nl, K - nl, n, tS)
+    rng = np.random.default_rng(5 + n + tS)
+    psi_flat = rng.normal(size=len(basis))
+    blocks = su2.coupled_blocks(lsec, rsec, n, tS)
+    psi = {k: np.zeros((lsec[k[0]][2], rsec[k[1]][2])) for k in blocks}
+    for c, (ia, al, ib, be) in enumerate(basis):
+        psi[(ia, ib)][al, be] = psi_flat[c]
+    got = su2.contract_scalar_products(lsec, rsec, n, tS, psi, pairs)
+    got_flat = np.array([got[(ia, ib)][al, be] for (ia, al, ib, be) in basis])
+    ref = m @ psi_flat
+    assert np.abs(ref).max() > 1e-2
+    assert np.allclose(got_flat, ref, atol=1e-10)
